@@ -1,0 +1,210 @@
+/* dvl.h -- C ABI of the MI355X dynamic-volume-line library.
+ *
+ * Dynamic volume lines (DVLs) over multi-field AMR data, after Zellmann,
+ * Demirci and Gudukbay, "Visual Analysis of Large Multi-Field AMR Data on
+ * GPUs Using Interactive Volume Lines" (arXiv 2306.11612).
+ *
+ * Two parts:
+ *   ordering (once per volume)   dvl_build_order
+ *   update (per TF/data change)  dvl_set_tf, dvl_update, dvl_read_bins
+ *
+ * Conventions
+ *   - Plain C types only.  "device" pointers are HIP device allocations on
+ *     the current device; "host" pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued on it; calls return before it completes
+ *     unless stated otherwise.
+ *   - Every call returns a dvl_status; on failure dvl_last_error() returns a
+ *     message (thread-local, valid until the next call on that thread).
+ *     No call ever throws or aborts.
+ *   - A volume may be used by one host thread at a time; distinct volumes
+ *     are independent.  Updates of one volume must be issued on one stream
+ *     (they share the volume's parameter block and workspace).
+ *   - The library owns the volume's internal device buffers (sorted fields,
+ *     levels, keys, permutation, workspace) and allocates them with
+ *     hipMalloc; dvl_destroy frees them.
+ */
+#ifndef DVL_H
+#define DVL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dvl_status;
+#define DVL_OK          0
+#define DVL_E_INVALID   1   /* an argument is out of its documented range */
+#define DVL_E_NOMEM     2   /* a device or host allocation failed */
+#define DVL_E_HIP       3   /* a HIP runtime call or kernel failed (sticky per volume) */
+#define DVL_E_STATE     4   /* call not allowed in the volume's state (e.g. a field has no TF) */
+#define DVL_E_OVERLAP   5   /* two cells share a Hilbert key: the AMR cells overlap */
+#define DVL_E_RANGE     6   /* data out of range: negative corner, level > 20, grid
+                               beyond 2^21 per axis, or a NaN field value */
+
+/* storage type of the field values; arithmetic is always fp32 */
+#define DVL_F32   0
+#define DVL_F16   1
+#define DVL_BF16  2
+
+/* how max(V_h) of Eq. 2/3 is obtained (section "Computing the Maximum Local
+ * Ensemble Variation") */
+#define DVL_VMAX_TF_RANGE 0  /* Eqs. 5-6: max over TF entries a in [min i_m, max j_m]
+                                of max_m A_m[a] - min_m A_m[a]; falls back to
+                                TF_BOUND when that is 0 (default) */
+#define DVL_VMAX_TF_BOUND 1  /* max_m max_{a in [i_m,j_m]} A_m[a] - min_m min A_m[a] */
+#define DVL_VMAX_EXACT    2  /* max over all cells of V_h (one extra pass) */
+
+/* arithmetic of the carry propagation of the Eq. 4 prefix sum across tiles */
+#define DVL_SCAN_FP64        0  /* default */
+#define DVL_SCAN_KAHAN_FP32  1  /* compensated fp32 */
+#define DVL_SCAN_NAIVE_FP32  2  /* plain fp32, for error studies only */
+
+typedef struct dvl_volume dvl_volume;
+
+/* ---------------------------------------------------------------------
+ * dvl_build_order -- one-time ordering (Background, AMR paragraph and
+ * Dynamic Volume Lines; GPU section: the Hilbert order is computed once and
+ * never changes, only the spacing does).
+ *
+ * Each AMR leaf cell is its lower corner (x, y, z) on the logical grid and
+ * its level (0 = finest, width 2^level).  The cell's key is the 3b-bit
+ * Hilbert index of its centroid's finest-level cell corner + 2^level / 2 on
+ * the 2^b cube, b = smallest b >= 1 with 2^b >= max(corner + 2^level)
+ * (b <= 21, so keys fit 63 bits).  Cells are radix-sorted by (key, original
+ * index); the level and every field are gathered into that order and each
+ * field's data range (min, max) is recorded.
+ *
+ *   n_cells        1 <= n_cells < 2^32
+ *   x, y, z        device int32[n_cells], original cell order, >= 0
+ *   level          device uint8[n_cells], <= 20
+ *   n_fields       M, 1 <= M <= 16
+ *   dtype          DVL_F32 | DVL_F16 | DVL_BF16 (storage of every field)
+ *   fields         host array of M device pointers, each [n_cells] values
+ *                  of `dtype` in original order
+ *   out            receives the new volume (NULL on failure)
+ *
+ * Inputs are only read, and may be freed once the call returns.  The call
+ * synchronises `stream`.  Errors: DVL_E_INVALID (arguments), DVL_E_RANGE
+ * (coordinates, levels or NaN values), DVL_E_OVERLAP (duplicate keys),
+ * DVL_E_NOMEM, DVL_E_HIP.
+ * ------------------------------------------------------------------- */
+dvl_status dvl_build_order(int64_t n_cells, const int32_t* x, const int32_t* y,
+                           const int32_t* z, const uint8_t* level, int32_t n_fields,
+                           int32_t dtype, const void* const* fields, void* stream,
+                           dvl_volume** out);
+
+/* Replace field m's values (a data change; the order is unchanged).
+ * values: device [n_cells] of the volume's dtype, original order.  Re-gathers
+ * into sorted order and refreshes the data range; synchronises `stream`.
+ * A previously set TF for m stays, with its window. */
+dvl_status dvl_set_field(dvl_volume* v, int32_t m, const void* values, void* stream);
+
+/* Data range [min, max] of field m (host outputs). */
+dvl_status dvl_field_range(const dvl_volume* v, int32_t m, float* vmin, float* vmax);
+
+/* ---------------------------------------------------------------------
+ * dvl_set_tf -- alpha transfer function of field m (section Interactive
+ * Transfer Function Updates).  The field value is normalised to the window
+ * [lo, hi] and mapped to entry clamp(floor(fmaf(x, s, b)), 0, n_tf - 1),
+ * s = (float)(n_tf / (hi - lo)), b = (float)(-lo * s); the entry's alpha is
+ * the intensity I(m, h) of Eq. 1 and, applied to a bin's mean, the bin
+ * height.
+ *
+ *   alpha   host float[n_tf], values in [0, 1]; copied, may be freed on return
+ *   n_tf    2 <= n_tf <= 4096, and M * n_tf <= 16384 over the volume
+ *   lo, hi  finite, lo < hi (use dvl_field_range for the data range)
+ *
+ * Host only; takes effect at the next dvl_update.  Waits for the previous
+ * update's parameter upload if it is still in flight.
+ * ------------------------------------------------------------------- */
+dvl_status dvl_set_tf(dvl_volume* v, int32_t m, const float* alpha, int32_t n_tf,
+                      float lo, float hi);
+
+typedef struct {
+    int32_t n_bins;          /* W: plot width in pixels, 1 <= W <= 2^20 */
+    float exponent;          /* P of Eqs. 2/3, 0 <= P <= 16 */
+    float min_importance;    /* >= 0; 0.025 in the paper's evaluation */
+    int32_t vmax_mode;       /* DVL_VMAX_* */
+    int32_t clamp_mode;      /* 0: f = max(fmin, (r s_L)^P) (default)
+                                1: f = (max(fmin, r) s_L)^P */
+    int32_t level_scale;     /* 1: s_L = 2^L (Eq. 3, default); 3: s_L = 8^L (cell volume) */
+    int32_t scan_mode;       /* DVL_SCAN_* */
+} dvl_params;
+
+/* Per-bin outputs, all device pointers owned by the caller.
+ *   first_cell, last_cell  uint32[W]: the bin holds sorted cells
+ *                          first..last (count = last - first + 1)
+ *   mean, vmin, vmax, y    float[M*W], index m*W + b: mean/min/max of the
+ *                          stored field value over the bin's cells and the
+ *                          height y = alpha_m[entry(mean)]
+ *   f_total                double[1]: F(max h) of Eq. 4
+ *   vmax_used              float[1]: the max(V_h) (or approximation) used
+ */
+typedef struct {
+    uint32_t* first_cell;
+    uint32_t* last_cell;
+    float* mean;
+    float* vmin;
+    float* vmax;
+    float* y;
+    double* f_total;
+    float* vmax_used;
+} dvl_bins;
+
+/* ---------------------------------------------------------------------
+ * dvl_update -- one volume-line update (Eqs. 1-4 and section Projecting
+ * Cells to 1D): per cell, TF lookup of every field, local variation V (Eq. 1),
+ * importance f = (V / max V * 2^L)^P with the minimum importance (Eq. 3),
+ * exclusive prefix E of f (Eq. 4), pixel interval [E W / F, (E + f) W / F);
+ * every bin b with the interval overlapping [b, b + 1) gets the cell (box
+ * basis; zero-width cells go to the bin holding their position); per bin
+ * and field the mean, min and max of the stored values and y = alpha(mean).
+ *
+ * Asynchronous on `stream`; no host synchronisation.  Requires a TF for
+ * every field (else DVL_E_STATE).  Outputs are complete when `stream`
+ * reaches the end of the enqueued work.  Errors: DVL_E_INVALID,
+ * DVL_E_STATE, DVL_E_NOMEM (workspace growth), DVL_E_HIP.
+ * ------------------------------------------------------------------- */
+dvl_status dvl_update(dvl_volume* v, const dvl_params* p, const dvl_bins* out, void* stream);
+
+/* Synchronise `stream`, then copy the bins to host arrays (any may be NULL):
+ * count/first/last uint32[W], mean/vmin/vmax/y float[M*W], f_total[1],
+ * vmax_used[1]. */
+dvl_status dvl_read_bins(const dvl_volume* v, const dvl_bins* bins, int32_t n_bins,
+                         void* stream, uint32_t* count, uint32_t* first, uint32_t* last,
+                         float* mean, float* vmin, float* vmax, float* y,
+                         double* f_total, float* vmax_used);
+
+/* Hilbert keys in ORIGINAL cell order and the permutation (perm[h] = original
+ * index of the h-th sorted cell), into caller-owned device arrays
+ * uint64[n_cells] and uint32[n_cells] (either may be NULL).  Asynchronous. */
+dvl_status dvl_export_order(const dvl_volume* v, uint64_t* keys, uint32_t* perm, void* stream);
+
+/* Sorted level and field arrays, into caller-owned device arrays
+ * (uint8[n_cells]; fields: host array of M device pointers, each
+ * [n_cells] of the volume's dtype; entries may be NULL).  Asynchronous. */
+dvl_status dvl_export_sorted(const dvl_volume* v, uint8_t* level, void* const* fields,
+                             void* stream);
+
+int64_t dvl_num_cells(const dvl_volume* v);
+int32_t dvl_num_fields(const dvl_volume* v);
+int32_t dvl_grid_bits(const dvl_volume* v);
+int32_t dvl_dtype(const dvl_volume* v);
+/* device bytes held by the volume (buffers and current workspace) */
+size_t dvl_volume_bytes(const dvl_volume* v);
+/* device workspace one update of this shape needs beyond the volume */
+size_t dvl_update_workspace_bytes(int64_t n_cells, int32_t n_fields, int32_t n_bins);
+
+/* Free the volume's device buffers (synchronises the device first). NULL ok. */
+void dvl_destroy(dvl_volume* v);
+
+/* Message of the calling thread's last failing call ("" if none). */
+const char* dvl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DVL_H */

@@ -1,0 +1,495 @@
+// One-time ordering: Hilbert keys at finest-level resolution, LSD radix
+// sort of (key, original index), gather of levels and fields into sorted
+// order, and per-field data ranges.
+//
+// Paper: Background (AMR cells snapped to the logical grid: lower corner +
+// level, width 2^L), Dynamic Volume Lines (cells represented by quantised
+// centroids, ordered along a Hilbert curve), GPU section (the order is
+// established once; only the spacing changes afterwards).
+#include "order.hpp"
+
+#include <algorithm>
+
+namespace dvl {
+
+// ===================================================================
+// extent: max(corner + 2^level) over all cells and axes, plus range checks
+// ===================================================================
+__global__ __launch_bounds__(256) void k_extent(int64_t n, const int32_t* __restrict__ x,
+                                                const int32_t* __restrict__ y,
+                                                const int32_t* __restrict__ z,
+                                                const uint8_t* __restrict__ level,
+                                                unsigned long long* __restrict__ out /* [0] max upper corner, [1] bad, [2] max level */) {
+    int64_t mx = 0;
+    uint32_t bad = 0, lmax = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int32_t cx = x[i], cy = y[i], cz = z[i];
+        const uint32_t L = level[i];
+        bad |= (cx < 0) | (cy < 0) | (cz < 0) | (L > 20u);
+        lmax = max(lmax, L);
+        const int64_t w = (int64_t)1 << (L & 31u);
+        const int64_t m = max(max((int64_t)cx, (int64_t)cy), (int64_t)cz) + w;
+        mx = max(mx, m);
+    }
+    // wave reduce then one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) {
+        const int l = lane_id() ^ o;
+        int lo = __builtin_amdgcn_ds_bpermute(l << 2, (int)(uint32_t)mx);
+        int hi = __builtin_amdgcn_ds_bpermute(l << 2, (int)(uint32_t)((uint64_t)mx >> 32));
+        mx = max(mx, (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+        bad |= (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)bad);
+        lmax = max(lmax, (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)lmax));
+    }
+    if (lane_id() == 0) {
+        atomicMax(&out[0], (unsigned long long)mx);
+        if (bad) atomicOr(&out[1], 1ull);
+        atomicMax(&out[2], (unsigned long long)lmax);
+    }
+}
+
+// ===================================================================
+// Hilbert index (Skilling 2004, "Programming the Hilbert curve"): the
+// axes are turned into the transposed index by undoing the recursive
+// construction's excess work plane by plane from the top, then Gray-coded;
+// the bits are interleaved with axis x most significant in every 3-bit
+// digit.  The final Gray correction is computed in closed form: its bit j is
+// the parity of the bits of the last axis above j.
+// ===================================================================
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1FFFFFu;
+    x = (x | (x << 32)) & 0x001F00000000FFFFull;
+    x = (x | (x << 16)) & 0x001F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t hilbert3(uint32_t a, uint32_t b, uint32_t c, int bits) {
+    for (int j = bits - 1; j >= 1; --j) {
+        const uint32_t Q = 1u << j, P = Q - 1u;
+        // axis 0 against itself: invert when set, exchanging with itself is a no-op
+        a ^= (a & Q) ? P : 0u;
+        if (b & Q) {
+            a ^= P;
+        } else {
+            const uint32_t t = (a ^ b) & P;
+            a ^= t;
+            b ^= t;
+        }
+        if (c & Q) {
+            a ^= P;
+        } else {
+            const uint32_t t = (a ^ c) & P;
+            a ^= t;
+            c ^= t;
+        }
+    }
+    b ^= a;
+    c ^= b;
+    uint32_t t = c >> 1;          // bit j of t = xor of bits > j of c
+    t ^= t >> 1;
+    t ^= t >> 2;
+    t ^= t >> 4;
+    t ^= t >> 8;
+    t ^= t >> 16;
+    const uint32_t mask = (bits >= 32) ? 0xFFFFFFFFu : ((1u << bits) - 1u);
+    t &= mask;
+    a ^= t;
+    b ^= t;
+    c ^= t;
+    return (spread3(a) << 2) | (spread3(b) << 1) | spread3(c);
+}
+
+__global__ __launch_bounds__(256) void k_keys(int64_t n, const int32_t* __restrict__ x,
+                                              const int32_t* __restrict__ y,
+                                              const int32_t* __restrict__ z,
+                                              const uint8_t* __restrict__ level, int bits,
+                                              uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t half = (1u << level[i]) >> 1;
+        keys[i] = hilbert3((uint32_t)x[i] + half, (uint32_t)y[i] + half, (uint32_t)z[i] + half, bits);
+        idx[i] = (uint32_t)i;
+    }
+}
+
+// ===================================================================
+// LSD radix sort, 8-bit digits.  Per pass:
+//   k_digit_hist   per-tile digit counts, stored digit-major [256][T]
+//   scan_u32       exclusive scan of that array (global bucket offsets)
+//   k_scatter      stable in-tile ranking (wave match of equal digits),
+//                  staging of the tile in digit order in LDS, then writes of
+//                  contiguous runs to the global offsets
+// ===================================================================
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                       // per thread
+constexpr int kSortTile = kSortThreads * kSortItems; // 4096 keys
+constexpr int kWavesPerSortTile = kSortThreads / kWave;
+constexpr int kRadix = 256;
+
+__global__ __launch_bounds__(kSortThreads) void k_digit_hist(int64_t n, const uint64_t* __restrict__ keys,
+                                                             int shift, int64_t n_tiles,
+                                                             uint32_t* __restrict__ counts) {
+    __shared__ uint32_t hist[kWavesPerSortTile][kRadix];
+    const int w = threadIdx.x / kWave;
+    for (int i = threadIdx.x; i < kWavesPerSortTile * kRadix; i += kSortThreads)
+        (&hist[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * kSortTile;
+#pragma unroll 4
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
+        if (i < n) {
+            const uint32_t d = (uint32_t)(keys[i] >> shift) & 0xFFu;
+            atomicAdd(&hist[w][d], 1u);
+        }
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < kWavesPerSortTile; ++q) s += hist[q][d];
+        counts[(int64_t)d * n_tiles + tile] = s;
+    }
+}
+
+// exclusive scan of uint32 (values and totals fit 32 bits: n_cells < 2^32)
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t* sh /* [kScanThreads/64] */,
+                                                        uint32_t* total) {
+    // wave inclusive scan (shuffles), then wave totals through LDS
+    uint32_t x = v;
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t t = (uint32_t)shfl_up_i((int)x, d);
+        if (lane_id() >= d) x += t;
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) sh[w] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int q = 0; q < (int)(blockDim.x / kWave); ++q) {
+        if (q < w) off += sh[q];
+        tot += sh[q];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t n, const uint32_t* __restrict__ in,
+                                                              uint32_t* __restrict__ partial) {
+    __shared__ uint32_t sh[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    uint32_t s = 0;
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint32_t tot;
+    block_excl_scan_u32(s, sh, &tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_partials(int64_t n_part, uint32_t* __restrict__ partial) {
+    __shared__ uint32_t sh[1024 / kWave];
+    uint32_t carry = 0;
+    for (int64_t b0 = 0; b0 < n_part; b0 += blockDim.x) {
+        const int64_t i = b0 + threadIdx.x;
+        const uint32_t v = i < n_part ? partial[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan_u32(v, sh, &tot);
+        if (i < n_part) partial[i] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(int64_t n, const uint32_t* __restrict__ in,
+                                                            const uint32_t* __restrict__ partial,
+                                                            uint32_t* __restrict__ out) {
+    __shared__ uint32_t sh[kScanThreads / kWave];
+    // blocked arrangement: thread t owns items [t*kScanItems, (t+1)*kScanItems)
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t i = base + r;
+        v[r] = i < n ? in[i] : 0u;
+        s += v[r];
+    }
+    uint32_t tot;
+    uint32_t run = partial[blockIdx.x] + block_excl_scan_u32(s, sh, &tot);
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t i = base + r;
+        if (i < n) out[i] = run;
+        run += v[r];
+    }
+}
+
+static dvl_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial,
+                           hipStream_t s) {
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, n, in, partial);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, nb, partial);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, n, in, partial, out);
+    DVL_HIP(hipGetLastError());
+    return DVL_OK;
+}
+
+int64_t scan_partial_count(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
+
+__global__ __launch_bounds__(kSortThreads) void k_scatter(int64_t n, const uint64_t* __restrict__ kin,
+                                                          const uint32_t* __restrict__ vin, int shift,
+                                                          int64_t n_tiles, const uint32_t* __restrict__ offs,
+                                                          uint64_t* __restrict__ kout,
+                                                          uint32_t* __restrict__ vout) {
+    __shared__ uint32_t whist[kWavesPerSortTile][kRadix];   // per-wave digit counts, then bases
+    __shared__ uint32_t tbase[kRadix];                      // tile-local start of each digit
+    __shared__ uint32_t gbase[kRadix];                      // global start of each digit for this tile
+    __shared__ uint32_t wsum[kSortThreads / kWave];
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
+
+    const int w = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int64_t tile = blockIdx.x;
+    const int64_t tbeg = tile * kSortTile;
+    const int n_here = (int)min((int64_t)kSortTile, n - tbeg);
+
+    for (int i = threadIdx.x; i < kWavesPerSortTile * kRadix; i += kSortThreads) (&whist[0][0])[i] = 0;
+    __syncthreads();
+
+    // each wave owns a contiguous quarter of the tile; round r covers 64 keys
+    uint64_t key[kSortItems];
+    uint32_t val[kSortItems];
+    uint32_t rank[kSortItems];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int li = w * (kWave * kSortItems) + r * kWave + lane;   // tile-local index
+        const bool ok = li < n_here;
+        key[r] = ok ? kin[tbeg + li] : 0ull;
+        val[r] = ok ? vin[tbeg + li] : 0u;
+        const uint32_t d = ok ? ((uint32_t)(key[r] >> shift) & 0xFFu) : 0u;
+        // lanes holding the same digit
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t b = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? b : ~b;
+        }
+        const uint32_t before = (uint32_t)__popcll(peers & lt);
+        const uint32_t old = ok ? whist[w][d] : 0u;
+        rank[r] = old + before;
+        // the lowest peer bumps the counter by the group size
+        if (ok && before == 0) whist[w][d] = old + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // per digit: wave bases inside the tile and the tile's digit start
+    if (threadIdx.x < kRadix) {
+        const int d = threadIdx.x;
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < kWavesPerSortTile; ++q) {
+            const uint32_t c = whist[q][d];
+            whist[q][d] = run;
+            run += c;
+        }
+        tbase[d] = run;   // tile count of digit d for now
+        gbase[d] = offs[(int64_t)d * n_tiles + tile];
+    }
+    __syncthreads();
+    // exclusive scan of the 256 tile counts (threads 0..255 hold one each)
+    {
+        const uint32_t c = threadIdx.x < kRadix ? tbase[threadIdx.x] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan_u32(c, wsum, &tot);
+        __syncthreads();
+        if (threadIdx.x < kRadix) tbase[threadIdx.x] = ex;
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int li = w * (kWave * kSortItems) + r * kWave + lane;
+        if (li < n_here) {
+            const uint32_t d = (uint32_t)(key[r] >> shift) & 0xFFu;
+            const uint32_t pos = tbase[d] + whist[w][d] + rank[r];
+            if (pos < (uint32_t)kSortTile) {
+                skey[pos] = key[r];
+                sval[pos] = val[r];
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_here; i += kSortThreads) {
+        const uint64_t k = skey[i];
+        const uint32_t d = (uint32_t)(k >> shift) & 0xFFu;
+        const int64_t g = (int64_t)gbase[d] + (i - (int64_t)tbase[d]);
+        if (g >= 0 && g < n) {
+            kout[g] = k;
+            vout[g] = sval[i];
+        }
+    }
+}
+
+// flag adjacent equal keys
+__global__ __launch_bounds__(256) void k_dup(int64_t n, const uint64_t* __restrict__ k,
+                                             unsigned long long* __restrict__ flag) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t d = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; i < n; i += stride)
+        d |= (k[i] == k[i - 1]);
+    if (__ballot(d) != 0ull && lane_id() == 0) atomicOr(flag, 1ull);
+}
+
+dvl_status radix_sort(int64_t n, int key_bits, uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp,
+                      uint32_t* vals_tmp, uint32_t* counts, uint32_t* partial, hipStream_t s,
+                      uint64_t** keys_out, uint32_t** vals_out) {
+    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+    const int passes = std::max(1, (key_bits + 7) / 8);
+    uint64_t* ka = keys; uint64_t* kb = keys_tmp;
+    uint32_t* va = vals; uint32_t* vb = vals_tmp;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, n, ka, shift,
+                           n_tiles, counts);
+        DVL_HIP(hipGetLastError());
+        dvl_status st = scan_u32(counts, counts, (int64_t)kRadix * n_tiles, partial, s);
+        if (st != DVL_OK) return st;
+        hipLaunchKernelGGL(k_scatter, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, n, ka, va, shift,
+                           n_tiles, counts, kb, vb);
+        DVL_HIP(hipGetLastError());
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    *keys_out = ka;
+    *vals_out = va;
+    return DVL_OK;
+}
+
+int64_t sort_tile_count(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+// ===================================================================
+// gather into sorted order; data ranges
+// ===================================================================
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(int64_t n, const uint32_t* __restrict__ perm,
+                                                const T* __restrict__ src, T* __restrict__ dst) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t p = perm[i];
+        if (p < (uint64_t)n) dst[i] = src[p];
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_range(int64_t n, const typename S::raw* __restrict__ v,
+                                               unsigned int* __restrict__ out /* [0] min key, [1] max key, [2] nan */) {
+    // order-preserving map of floats to unsigned ints
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u, nan = 0u;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float f = to_f32(S{}, v[i]);
+        if (f != f) { nan = 1u; continue; }
+        uint32_t u = __float_as_uint(f);
+        u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+        lo = min(lo, u);
+        hi = max(hi, u);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const int l = lane_id() ^ o;
+        lo = min(lo, (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)lo));
+        hi = max(hi, (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)hi));
+        nan |= (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)nan);
+    }
+    if (lane_id() == 0) {
+        atomicMin(&out[0], lo);
+        atomicMax(&out[1], hi);
+        if (nan) atomicOr(&out[2], 1u);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_back(int64_t n, const uint32_t* __restrict__ perm,
+                                                      const T* __restrict__ sorted, T* __restrict__ orig) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t p = perm[i];
+        if (p < (uint64_t)n) orig[p] = sorted[i];
+    }
+}
+
+static unsigned grid_for(int64_t n, int per_block = 256, int max_blocks = 8192) {
+    int64_t g = (n + per_block - 1) / per_block;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, max_blocks));
+}
+
+dvl_status launch_extent(int64_t n, const int32_t* x, const int32_t* y, const int32_t* z,
+                         const uint8_t* level, unsigned long long* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_extent, dim3(grid_for(n)), dim3(256), 0, s, n, x, y, z, level, out);
+    DVL_HIP(hipGetLastError());
+    return DVL_OK;
+}
+
+dvl_status launch_keys(int64_t n, const int32_t* x, const int32_t* y, const int32_t* z,
+                       const uint8_t* level, int bits, uint64_t* keys, uint32_t* idx, hipStream_t s) {
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(256), 0, s, n, x, y, z, level, bits, keys, idx);
+    DVL_HIP(hipGetLastError());
+    return DVL_OK;
+}
+
+dvl_status launch_dup(int64_t n, const uint64_t* keys, unsigned long long* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_dup, dim3(grid_for(n)), dim3(256), 0, s, n, keys, flag);
+    DVL_HIP(hipGetLastError());
+    return DVL_OK;
+}
+
+dvl_status launch_gather(int64_t n, const uint32_t* perm, const void* src, void* dst, int elem_bytes,
+                         hipStream_t s) {
+    if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_gather<uint32_t>, dim3(grid_for(n)), dim3(256), 0, s, n, perm,
+                           (const uint32_t*)src, (uint32_t*)dst);
+    else if (elem_bytes == 2)
+        hipLaunchKernelGGL(k_gather<uint16_t>, dim3(grid_for(n)), dim3(256), 0, s, n, perm,
+                           (const uint16_t*)src, (uint16_t*)dst);
+    else
+        hipLaunchKernelGGL(k_gather<uint8_t>, dim3(grid_for(n)), dim3(256), 0, s, n, perm,
+                           (const uint8_t*)src, (uint8_t*)dst);
+    DVL_HIP(hipGetLastError());
+    return DVL_OK;
+}
+
+dvl_status launch_scatter_back(int64_t n, const uint32_t* perm, const void* sorted, void* orig,
+                               int elem_bytes, hipStream_t s) {
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_scatter_back<uint64_t>, dim3(grid_for(n)), dim3(256), 0, s, n, perm,
+                           (const uint64_t*)sorted, (uint64_t*)orig);
+    else
+        return DVL_E_INVALID;
+    DVL_HIP(hipGetLastError());
+    return DVL_OK;
+}
+
+dvl_status launch_range(int64_t n, int dtype, const void* v, unsigned int* out, hipStream_t s) {
+    if (dtype == DVL_F32)
+        hipLaunchKernelGGL(k_range<F32>, dim3(grid_for(n)), dim3(256), 0, s, n, (const float*)v, out);
+    else if (dtype == DVL_F16)
+        hipLaunchKernelGGL(k_range<F16>, dim3(grid_for(n)), dim3(256), 0, s, n, (const uint16_t*)v, out);
+    else
+        hipLaunchKernelGGL(k_range<BF16>, dim3(grid_for(n)), dim3(256), 0, s, n, (const uint16_t*)v, out);
+    DVL_HIP(hipGetLastError());
+    return DVL_OK;
+}
+
+}  // namespace dvl

@@ -1,0 +1,279 @@
+"""Thin ctypes binding of ``libdvl.so`` (the C ABI in ``include/dvl.h``).
+
+Argument marshalling only: every step of the ordering and the update runs in
+the HIP kernels behind the C ABI.  PyTorch provides device memory and the
+current stream.  There is no CPU fallback: if the library is not built this
+module raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libdvl.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "dvl.h")
+
+OK, E_INVALID, E_NOMEM, E_HIP, E_STATE, E_OVERLAP, E_RANGE = range(7)
+F32, F16, BF16 = 0, 1, 2
+VMAX_TF_RANGE, VMAX_TF_BOUND, VMAX_EXACT = 0, 1, 2
+SCAN_FP64, SCAN_KAHAN_FP32, SCAN_NAIVE_FP32 = 0, 1, 2
+
+_DTYPE_CODE = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+_CODE_DTYPE = {v: k for k, v in _DTYPE_CODE.items()}
+
+
+class DvlError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+class dvl_params(C.Structure):
+    _fields_ = [("n_bins", C.c_int32), ("exponent", C.c_float), ("min_importance", C.c_float),
+                ("vmax_mode", C.c_int32), ("clamp_mode", C.c_int32), ("level_scale", C.c_int32),
+                ("scan_mode", C.c_int32)]
+
+
+class dvl_bins(C.Structure):
+    _fields_ = [("first_cell", C.c_void_p), ("last_cell", C.c_void_p), ("mean", C.c_void_p),
+                ("vmin", C.c_void_p), ("vmax", C.c_void_p), ("y", C.c_void_p),
+                ("f_total", C.c_void_p), ("vmax_used", C.c_void_p)]
+
+
+_lib = None
+
+
+def declared_symbols(header: str = HEADER) -> list[str]:
+    """Names of the functions ``include/dvl.h`` declares."""
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dvl_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib():
+    """Load libdvl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library missing: {LIB_PATH}; build it with "
+                           "`python -m paper_2306_11612_amd.build` (there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
+    sig = {
+        "dvl_build_order": (i32, [i64, vp, vp, vp, vp, i32, i32, vp, vp, C.POINTER(vp)]),
+        "dvl_set_field": (i32, [vp, i32, vp, vp]),
+        "dvl_field_range": (i32, [vp, i32, C.POINTER(f32), C.POINTER(f32)]),
+        "dvl_set_tf": (i32, [vp, i32, vp, i32, f32, f32]),
+        "dvl_update": (i32, [vp, C.POINTER(dvl_params), C.POINTER(dvl_bins), vp]),
+        "dvl_read_bins": (i32, [vp, C.POINTER(dvl_bins), i32, vp] + [vp] * 9),
+        "dvl_export_order": (i32, [vp, vp, vp, vp]),
+        "dvl_export_sorted": (i32, [vp, vp, vp, vp]),
+        "dvl_num_cells": (i64, [vp]),
+        "dvl_num_fields": (i32, [vp]),
+        "dvl_grid_bits": (i32, [vp]),
+        "dvl_dtype": (i32, [vp]),
+        "dvl_volume_bytes": (C.c_size_t, [vp]),
+        "dvl_update_workspace_bytes": (C.c_size_t, [i64, i32, i32]),
+        "dvl_destroy": (None, [vp]),
+        "dvl_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise DvlError(status, where, lib().dvl_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype=None) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+class Bins:
+    """Caller-owned device outputs of one update (``dvl_bins``)."""
+
+    def __init__(self, n_bins: int, n_fields: int, device=None):
+        device = device or torch.device("cuda", torch.cuda.current_device())
+        self.n_bins, self.n_fields = int(n_bins), int(n_fields)
+        W, M = self.n_bins, self.n_fields
+        self.first_cell = torch.empty(W, dtype=torch.int32, device=device)
+        self.last_cell = torch.empty(W, dtype=torch.int32, device=device)
+        self.mean = torch.empty(M, W, dtype=torch.float32, device=device)
+        self.vmin = torch.empty(M, W, dtype=torch.float32, device=device)
+        self.vmax = torch.empty(M, W, dtype=torch.float32, device=device)
+        self.y = torch.empty(M, W, dtype=torch.float32, device=device)
+        self.f_total = torch.empty(1, dtype=torch.float64, device=device)
+        self.vmax_used = torch.empty(1, dtype=torch.float32, device=device)
+
+    def struct(self) -> dvl_bins:
+        return dvl_bins(self.first_cell.data_ptr(), self.last_cell.data_ptr(), self.mean.data_ptr(),
+                        self.vmin.data_ptr(), self.vmax.data_ptr(), self.y.data_ptr(),
+                        self.f_total.data_ptr(), self.vmax_used.data_ptr())
+
+
+def params(n_bins: int, exponent: float = 1.0, min_importance: float = 0.025,
+           vmax_mode: int = VMAX_TF_RANGE, clamp_mode: int = 0, level_scale: int = 1,
+           scan_mode: int = SCAN_FP64) -> dvl_params:
+    return dvl_params(int(n_bins), float(exponent), float(min_importance), int(vmax_mode),
+                      int(clamp_mode), int(level_scale), int(scan_mode))
+
+
+# ---------------------------------------------------------------- C-ABI mirrors
+
+def build_order(x, y, z, level, fields, stream=None) -> "Volume":
+    """dvl_build_order: one-time Hilbert ordering of the cells."""
+    x, y, z = _dev(x, torch.int32), _dev(y, torch.int32), _dev(z, torch.int32)
+    level = _dev(level, torch.uint8)
+    fields = [_dev(f) for f in fields]
+    if not fields:
+        raise ValueError("need at least one field")
+    dt = fields[0].dtype
+    if dt not in _DTYPE_CODE or any(f.dtype != dt for f in fields):
+        raise ValueError("fields must share one of float32 / float16 / bfloat16")
+    arr = (C.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
+    out = C.c_void_p()
+    st = lib().dvl_build_order(x.numel(), _ptr(x), _ptr(y), _ptr(z), _ptr(level), len(fields),
+                               _DTYPE_CODE[dt], C.cast(arr, C.c_void_p), _stream_ptr(stream),
+                               C.byref(out))
+    _check(st, "dvl_build_order")
+    return Volume(out)
+
+
+def set_tf(vol: "Volume", m: int, alpha, lo: float, hi: float):
+    """dvl_set_tf: alpha TF of field m with normalisation window [lo, hi]."""
+    a = np.ascontiguousarray(np.asarray(alpha, dtype=np.float32))
+    _check(lib().dvl_set_tf(vol.handle, int(m), a.ctypes.data_as(C.c_void_p), a.size,
+                            float(lo), float(hi)), "dvl_set_tf")
+
+
+def update(vol: "Volume", p: dvl_params, bins: Bins, stream=None):
+    """dvl_update: enqueue one update on the stream."""
+    b = bins.struct()
+    _check(lib().dvl_update(vol.handle, C.byref(p), C.byref(b), _stream_ptr(stream)), "dvl_update")
+
+
+def read_bins(vol: "Volume", bins: Bins, stream=None) -> dict:
+    """dvl_read_bins: synchronise and copy the bins to host numpy arrays."""
+    W, M = bins.n_bins, bins.n_fields
+    count = np.empty(W, np.uint32); first = np.empty(W, np.uint32); last = np.empty(W, np.uint32)
+    mean = np.empty((M, W), np.float32); vmin = np.empty((M, W), np.float32)
+    vmax = np.empty((M, W), np.float32); y = np.empty((M, W), np.float32)
+    ft = np.empty(1, np.float64); vu = np.empty(1, np.float32)
+    b = bins.struct()
+    P = lambda a: a.ctypes.data_as(C.c_void_p)
+    _check(lib().dvl_read_bins(vol.handle, C.byref(b), W, _stream_ptr(stream), P(count), P(first),
+                               P(last), P(mean), P(vmin), P(vmax), P(y), P(ft), P(vu)), "dvl_read_bins")
+    return {"count": count, "first": first, "last": last, "mean": mean, "vmin": vmin, "vmax": vmax,
+            "y": y, "f_total": float(ft[0]), "vmax_used": float(vu[0])}
+
+
+class Volume:
+    """A volume in Hilbert order, resident on the device (owns a dvl_volume*)."""
+
+    def __init__(self, handle: C.c_void_p):
+        self.handle = handle
+
+    # conveniences over the C-ABI mirrors
+    build = staticmethod(build_order)
+
+    @property
+    def n(self) -> int:
+        return int(lib().dvl_num_cells(self.handle))
+
+    @property
+    def m(self) -> int:
+        return int(lib().dvl_num_fields(self.handle))
+
+    @property
+    def bits(self) -> int:
+        return int(lib().dvl_grid_bits(self.handle))
+
+    @property
+    def dtype(self):
+        return _CODE_DTYPE[int(lib().dvl_dtype(self.handle))]
+
+    @property
+    def nbytes(self) -> int:
+        return int(lib().dvl_volume_bytes(self.handle))
+
+    def field_range(self, m: int):
+        lo, hi = C.c_float(), C.c_float()
+        _check(lib().dvl_field_range(self.handle, int(m), C.byref(lo), C.byref(hi)), "dvl_field_range")
+        return lo.value, hi.value
+
+    def set_field(self, m: int, values: torch.Tensor, stream=None):
+        v = _dev(values, self.dtype)
+        _check(lib().dvl_set_field(self.handle, int(m), _ptr(v), _stream_ptr(stream)), "dvl_set_field")
+
+    def set_tf(self, m: int, alpha, lo: float | None = None, hi: float | None = None):
+        if lo is None or hi is None:
+            dlo, dhi = self.field_range(m)
+            lo = dlo if lo is None else lo
+            hi = dhi if hi is None else hi
+            if not hi > lo:
+                hi = np.nextafter(np.float32(lo), np.float32(np.inf))
+        set_tf(self, m, alpha, lo, hi)
+
+    def update(self, bins: Bins, stream=None, **kw):
+        update(self, params(bins.n_bins, **kw), bins, stream)
+
+    def read_bins(self, bins: Bins, stream=None) -> dict:
+        return read_bins(self, bins, stream)
+
+    def export_order(self, stream=None):
+        """(keys uint64-as-int64 [n] in original order, perm int32 [n])."""
+        n = self.n
+        keys = torch.empty(n, dtype=torch.int64, device="cuda")
+        perm = torch.empty(n, dtype=torch.int32, device="cuda")
+        _check(lib().dvl_export_order(self.handle, _ptr(keys), _ptr(perm), _stream_ptr(stream)),
+               "dvl_export_order")
+        return keys, perm
+
+    def export_sorted(self, stream=None):
+        n, M = self.n, self.m
+        level = torch.empty(n, dtype=torch.uint8, device="cuda")
+        fields = [torch.empty(n, dtype=self.dtype, device="cuda") for _ in range(M)]
+        arr = (C.c_void_p * M)(*[f.data_ptr() for f in fields])
+        _check(lib().dvl_export_sorted(self.handle, _ptr(level), C.cast(arr, C.c_void_p),
+                                       _stream_ptr(stream)), "dvl_export_sorted")
+        return level, fields
+
+    def close(self):
+        if self.handle:
+            lib().dvl_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def update_workspace_bytes(n_cells: int, n_fields: int, n_bins: int) -> int:
+    return int(lib().dvl_update_workspace_bytes(int(n_cells), int(n_fields), int(n_bins)))

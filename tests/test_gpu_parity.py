@@ -1,0 +1,226 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Keys and the permutation must match bit-exactly; bins are reconciled as
+described in parity.py (edge tolerance 1e-6 on the normalised axis, mean
+relative 1e-5, min/max bitwise)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_cases import check_order, dvl, random_amr, run_case, subset, tfs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dvl()
+
+
+# ---------------------------------------------------------------- ordering
+
+@pytest.mark.parametrize("seed,base,levels", [(0, 4, 3), (1, 6, 4), (2, 3, 2), (3, 8, 3)])
+def test_order_random_amr(seed, base, levels):
+    D = dvl()
+    vol = random_amr(seed, base, levels)
+    dev = vol.to("cuda")
+    print(f"[order] seed={seed} n={vol.n}", flush=True)
+    V = D.build_order(dev.x, dev.y, dev.z, dev.level, dev.fields)
+    try:
+        check_order(V, vol)
+    finally:
+        V.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 4095, 4097, 12345])
+def test_order_ragged_sizes(n):
+    D = dvl()
+    vol = subset(random_amr(7, 16, 3, 0.3), n, seed=n)
+    dev = vol.to("cuda")
+    print(f"[order] n={n}", flush=True)
+    V = D.build_order(dev.x, dev.y, dev.z, dev.level, dev.fields)
+    try:
+        check_order(V, vol)
+        lev, fl = V.export_sorted()
+        _, perm = V.export_order()
+        p = perm.cpu().numpy().view(np.uint32)
+        assert np.array_equal(lev.cpu().numpy(), vol.level.numpy()[p])
+        for m in range(vol.m):
+            assert np.array_equal(fl[m].cpu().numpy(), vol.fields[m].numpy()[p])
+    finally:
+        V.close()
+
+
+def test_order_cfg1_grid():
+    import synth
+    D = dvl()
+    vol = synth.cfg1()
+    dev = vol.to("cuda")
+    V = D.build_order(dev.x, dev.y, dev.z, dev.level, dev.fields)
+    try:
+        o = check_order(V, vol)
+        assert o.bits == 6
+    finally:
+        V.close()
+
+
+# ---------------------------------------------------------------- update
+
+def test_cfg1_grid_update():
+    import synth
+    vol = synth.cfg1()
+    run_case(vol, tfs(synth.SEED + 1, 4, n_cp=(4, 4)), 1024, label="cfg1")
+
+
+def test_uniform_variation_is_exactly_linear():
+    """TFs constant 1 and 0 give V = max V at every cell: with N = 2^18 and
+    W = 2^10 every GPU operation is exact, so bin b is cells 256b..256b+255."""
+    import synth
+    D = dvl()
+    vol = synth.cfg1()
+    A = np.stack([np.ones(256, np.float32), np.zeros(256, np.float32)] * 2)
+    g, ob, rep = run_case(vol, A, 1024, label="uniform-variation")
+    assert np.array_equal(g["first"], np.arange(1024, dtype=np.uint32) * 256)
+    assert np.array_equal(g["count"], np.full(1024, 256, np.uint32))
+    assert rep.edges_moved == 0
+
+
+@pytest.mark.parametrize("exponent,fmin,vmax_mode,clamp,lscale,W", [
+    (1.0, 0.025, 0, 0, 1, 1920),
+    (1.0, 0.025, 1, 0, 1, 1024),
+    (1.0, 0.025, 2, 0, 1, 1920),
+    (2.0, 0.025, 0, 0, 1, 1920),
+    (5.0, 0.025, 0, 0, 1, 3840),
+    (0.0, 0.025, 0, 0, 1, 500),
+    (0.5, 0.25, 0, 0, 1, 777),
+    (3.0, 0.0, 0, 0, 1, 1920),
+    (1.0, 0.025, 0, 1, 1, 1920),
+    (1.0, 0.025, 0, 0, 3, 1920),
+    (2.0, 0.1, 2, 1, 3, 257),
+])
+def test_small_amr_params(exponent, fmin, vmax_mode, clamp, lscale, W):
+    import synth
+    vol = synth.make_amr(16, (0.4, 0.3, 0.2), 4, 31, octaves=3, field_octaves=2)
+    run_case(vol, tfs(31, 4), W, exponent, fmin, vmax_mode, clamp, lscale,
+             label=f"amr16 p={exponent}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+def test_sixteen_bit_storage(dtype):
+    import synth
+    vol = synth.make_amr(16, (0.4, 0.3), 4, 41, octaves=3, field_octaves=2)
+    run_case(vol, tfs(41, 4), 1920, dtype=dtype, label=str(dtype))
+
+
+@pytest.mark.parametrize("scan_mode", [0, 1])
+def test_carry_modes(scan_mode):
+    import synth
+    vol = synth.make_amr(24, (0.4, 0.3, 0.2), 4, 51, octaves=3, field_octaves=2)
+    run_case(vol, tfs(51, 4), 1920, scan_mode=scan_mode, label=f"scan{scan_mode}")
+
+
+@pytest.mark.parametrize("n", [1, 5, 255, 257, 4096, 4097, 9000])
+def test_ragged_cell_counts(n):
+    vol = subset(random_amr(9, 16, 3, 0.3, n_fields=2), n, seed=n)
+    run_case(vol, tfs(n, 2), 64, label=f"ragged {n}")
+
+
+def test_more_bins_than_cells():
+    """Cells wider than a pixel: interior bins hold exactly one cell."""
+    vol = random_amr(11, 6, 3, 0.4, n_fields=3)
+    g, ob, rep = run_case(vol, tfs(11, 3), 3840, exponent=2.0, label="wide cells")
+    assert np.any(g["count"] == 1)
+
+
+def test_single_bin():
+    vol = random_amr(12, 8, 3, 0.4, n_fields=2)
+    g, _, _ = run_case(vol, tfs(12, 2), 1, label="W=1")
+    assert g["first"][0] == 0 and g["last"][0] == vol.n - 1
+
+
+def test_zero_total_width_is_linear():
+    """One field: V = 0 everywhere; with minimum importance 0 every f is 0
+    and the update falls back to the linear map."""
+    vol = random_amr(13, 8, 3, 0.4, n_fields=1)
+    g, ob, rep = run_case(vol, tfs(13, 1), 100, fmin=0.0, label="degenerate")
+    assert ob.degenerate
+    assert g["f_total"] == vol.n
+
+
+def test_determinism():
+    import synth
+    D = dvl()
+    vol = synth.make_amr(16, (0.4, 0.3), 4, 61, octaves=3, field_octaves=2).to("cuda")
+    V = D.build_order(vol.x, vol.y, vol.z, vol.level, vol.fields)
+    try:
+        A = tfs(61, 4)
+        for m in range(4):
+            V.set_tf(m, A[m])
+        outs = []
+        for _ in range(3):
+            b = D.Bins(1920, 4)
+            V.update(b, exponent=2.0)
+            outs.append(V.read_bins(b))
+        for k in ("first", "last", "mean", "vmin", "vmax", "y"):
+            assert np.array_equal(outs[0][k], outs[1][k]) and np.array_equal(outs[0][k], outs[2][k]), k
+    finally:
+        V.close()
+
+
+def test_cfg2_scaled():
+    """The 3-level AMR workload at base 64 (about 1.5 M cells)."""
+    import synth
+    vol = synth.cfg2(device="cuda", base=64).to("cpu")
+    run_case(vol, tfs(synth.SEED + 2, 4, n_cp=(4, 4)), 1920, label="cfg2/base64")
+
+
+# ---------------------------------------------------------------- errors
+
+def test_error_paths():
+    D = dvl()
+    vol = random_amr(21, 4, 2).to("cuda")
+    # overlapping cells: a coarse cell and one of its own sub-cells
+    x = torch.tensor([0, 1], dtype=torch.int32, device="cuda")
+    lv = torch.tensor([1, 0], dtype=torch.uint8, device="cuda")
+    f = torch.ones(2, device="cuda")
+    with pytest.raises(D.DvlError) as e:
+        D.build_order(x, x, x, lv, [f])
+    assert e.value.status == 5
+    with pytest.raises(D.DvlError) as e:
+        D.build_order(-x - 1, x, x, torch.zeros_like(lv), [f])
+    assert e.value.status == 6
+    with pytest.raises(D.DvlError) as e:
+        D.build_order(x, x, x, torch.full_like(lv, 21), [f])
+    assert e.value.status == 6
+    nanf = vol.fields[0].clone()
+    nanf[3] = float("nan")
+    with pytest.raises(D.DvlError) as e:
+        D.build_order(vol.x, vol.y, vol.z, vol.level, [nanf])
+    assert e.value.status == 6
+    V = D.build_order(vol.x, vol.y, vol.z, vol.level, vol.fields)
+    try:
+        b = D.Bins(16, vol.m)
+        with pytest.raises(D.DvlError) as e:
+            V.update(b)
+        assert e.value.status == 4            # no TF yet
+        for m in range(vol.m):
+            V.set_tf(m, np.linspace(0, 1, 256))
+        with pytest.raises(D.DvlError) as e:
+            D.set_tf(V, 0, np.ones(4), 1.0, 1.0)
+        assert e.value.status == 1
+        with pytest.raises(D.DvlError) as e:
+            D.set_tf(V, 9, np.ones(4), 0.0, 1.0)
+        assert e.value.status == 1
+        for bad in (dict(exponent=-1.0), dict(exponent=17.0), dict(min_importance=-0.1),
+                    dict(vmax_mode=3), dict(level_scale=2), dict(scan_mode=7)):
+            with pytest.raises(D.DvlError) as e:
+                V.update(b, **bad)
+            assert e.value.status == 1, bad
+        V.update(b)
+        g = V.read_bins(b)
+        assert g["count"].sum() >= vol.n
+    finally:
+        V.close()
