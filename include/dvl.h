@@ -189,6 +189,19 @@ dvl_status dvl_export_order(const dvl_volume* v, uint64_t* keys, uint32_t* perm,
 dvl_status dvl_export_sorted(const dvl_volume* v, uint8_t* level, void* const* fields,
                              void* stream);
 
+/* ---------------------------------------------------------------------
+ * Per-kernel timing of updates (profiling aid).  While enabled, every
+ * dvl_update records HIP events on its stream around each of its kernels:
+ * phase 0 exact max(V) (VMAX_EXACT only), 1 tile sums of the importance,
+ * 2 carry scan, 3 projection + bin reduction, 4 edge-bin merge.
+ * dvl_kernel_times synchronises on the recorded events, returns the summed
+ * milliseconds per phase (ms[5]) over the updates since the last call and
+ * their number, and resets the sums.  Enabling adds a few microseconds per
+ * update.
+ * ------------------------------------------------------------------- */
+dvl_status dvl_set_timing(dvl_volume* v, int32_t enable);
+dvl_status dvl_kernel_times(dvl_volume* v, double* ms, int32_t* n_updates);
+
 int64_t dvl_num_cells(const dvl_volume* v);
 int32_t dvl_num_fields(const dvl_volume* v);
 int32_t dvl_grid_bits(const dvl_volume* v);

@@ -99,6 +99,11 @@ struct dvl_volume {
     UpdWorkspace wsv{};
     dvl_status sticky = DVL_OK;
     size_t bytes = 0;
+    // optional per-kernel timing
+    bool timing = false;
+    std::vector<std::vector<hipEvent_t>> ev_pool, ev_pending;
+    double phase_ms[kPhases] = {};
+    int32_t timed_updates = 0;
 };
 
 namespace {
@@ -444,7 +449,18 @@ dvl_status dvl_update(dvl_volume* v, const dvl_params* p, const dvl_bins* out, v
     a.y = out->y;
     a.f_total = out->f_total;
     a.vmax_used = out->vmax_used;
-    dvl_status st = launch_update(a, v->n_cu, s);
+    hipEvent_t* ev = nullptr;
+    if (v->timing) {
+        if (v->ev_pool.empty()) {
+            std::vector<hipEvent_t> set(kPhases + 1);
+            for (auto& e : set) DVL_HIP(hipEventCreate(&e));
+            v->ev_pool.push_back(set);
+        }
+        v->ev_pending.push_back(v->ev_pool.back());
+        v->ev_pool.pop_back();
+        ev = v->ev_pending.back().data();
+    }
+    dvl_status st = launch_update(a, v->n_cu, s, ev);
     if (st != DVL_OK) v->sticky = st;
     return st;
 }
@@ -501,6 +517,35 @@ dvl_status dvl_export_sorted(const dvl_volume* v, uint8_t* level, void* const* f
     return DVL_OK;
 }
 
+dvl_status dvl_set_timing(dvl_volume* v, int32_t enable) {
+    g_err.clear();
+    if (dvl_status st = check_sticky(v)) return st;
+    v->timing = enable != 0;
+    return DVL_OK;
+}
+
+dvl_status dvl_kernel_times(dvl_volume* v, double* ms, int32_t* n_updates) {
+    g_err.clear();
+    if (dvl_status st = check_sticky(v)) return st;
+    for (auto& set : v->ev_pending) {
+        DVL_HIP(hipEventSynchronize(set[kPhases]));
+        for (int p = 0; p < kPhases; ++p) {
+            float t = 0.0f;
+            DVL_HIP(hipEventElapsedTime(&t, set[p], set[p + 1]));
+            v->phase_ms[p] += t;
+        }
+        v->timed_updates += 1;
+        v->ev_pool.push_back(set);
+    }
+    v->ev_pending.clear();
+    if (ms)
+        for (int p = 0; p < kPhases; ++p) ms[p] = v->phase_ms[p];
+    if (n_updates) *n_updates = v->timed_updates;
+    for (int p = 0; p < kPhases; ++p) v->phase_ms[p] = 0.0;
+    v->timed_updates = 0;
+    return DVL_OK;
+}
+
 int64_t dvl_num_cells(const dvl_volume* v) { return v ? v->n : 0; }
 int32_t dvl_num_fields(const dvl_volume* v) { return v ? v->M : 0; }
 int32_t dvl_grid_bits(const dvl_volume* v) { return v ? v->bits : 0; }
@@ -516,6 +561,9 @@ void dvl_destroy(dvl_volume* v) {
     if (v->keys_s) (void)hipFree(v->keys_s);
     if (v->perm) (void)hipFree(v->perm);
     if (v->ws) (void)hipFree(v->ws);
+    for (auto* pool : {&v->ev_pool, &v->ev_pending})
+        for (auto& set : *pool)
+            for (auto e : set) (void)hipEventDestroy(e);
     for (int r = 0; r < kRing; ++r) {
         if (v->param_dev[r]) (void)hipFree(v->param_dev[r]);
         if (v->param_host[r]) (void)hipHostFree(v->param_host[r]);

@@ -808,16 +808,23 @@ __global__ __launch_bounds__(256) void k_edges(UpdArgs a) {
 // ------------------------------------------------------------------ launcher
 
 template <int MT, typename S>
-static dvl_status launch_typed(const UpdArgs& a, int n_cu, hipStream_t s) {
+static dvl_status launch_typed(const UpdArgs& a, int n_cu, hipStream_t s, hipEvent_t* ev) {
     const size_t lds = (size_t)a.tf_total * sizeof(float);
     const int64_t wg_needed = (a.n_tiles + (kUpdThreads / kWave) - 1) / (kUpdThreads / kWave);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(wg_needed, (int64_t)n_cu * 8));
+    auto mark = [&](int i) -> dvl_status {
+        if (ev) DVL_HIP(hipEventRecord(ev[i], s));
+        return DVL_OK;
+    };
+    if (dvl_status st = mark(0)) return st;
     if (a.vmax_exact) {
         hipLaunchKernelGGL((k_vmax_exact<MT, S>), dim3(grid), dim3(kUpdThreads), lds, s, a);
         DVL_HIP(hipGetLastError());
     }
+    if (dvl_status st = mark(1)) return st;
     hipLaunchKernelGGL((k_tile_sums<MT, S>), dim3(grid), dim3(kUpdThreads), lds, s, a);
     DVL_HIP(hipGetLastError());
+    if (dvl_status st = mark(2)) return st;
     if (a.scan_mode == DVL_SCAN_KAHAN_FP32)
         hipLaunchKernelGGL(k_carry<AccKahan32>, dim3(1), dim3(kCarryThreads), 0, s, a);
     else if (a.scan_mode == DVL_SCAN_NAIVE_FP32)
@@ -825,33 +832,35 @@ static dvl_status launch_typed(const UpdArgs& a, int n_cu, hipStream_t s) {
     else
         hipLaunchKernelGGL(k_carry<AccF64>, dim3(1), dim3(kCarryThreads), 0, s, a);
     DVL_HIP(hipGetLastError());
+    if (dvl_status st = mark(3)) return st;
     hipLaunchKernelGGL((k_bin<MT, S>), dim3(grid), dim3(kUpdThreads), lds, s, a);
     DVL_HIP(hipGetLastError());
+    if (dvl_status st = mark(4)) return st;
     const unsigned g4 = (unsigned)((a.W + 3) / 4);
     hipLaunchKernelGGL((k_edges<MT>), dim3(g4), dim3(256), 0, s, a);
     DVL_HIP(hipGetLastError());
-    return DVL_OK;
+    return mark(5);
 }
 
 template <typename S>
-static dvl_status launch_m(const UpdArgs& a, int n_cu, hipStream_t s) {
+static dvl_status launch_m(const UpdArgs& a, int n_cu, hipStream_t s, hipEvent_t* ev) {
     switch (a.M) {
-        case 1: return launch_typed<1, S>(a, n_cu, s);
-        case 2: return launch_typed<2, S>(a, n_cu, s);
-        case 3: return launch_typed<3, S>(a, n_cu, s);
-        case 4: return launch_typed<4, S>(a, n_cu, s);
-        case 5: return launch_typed<5, S>(a, n_cu, s);
-        case 6: return launch_typed<6, S>(a, n_cu, s);
-        case 7: return launch_typed<7, S>(a, n_cu, s);
-        case 8: return launch_typed<8, S>(a, n_cu, s);
-        default: return launch_typed<16, S>(a, n_cu, s);
+        case 1: return launch_typed<1, S>(a, n_cu, s, ev);
+        case 2: return launch_typed<2, S>(a, n_cu, s, ev);
+        case 3: return launch_typed<3, S>(a, n_cu, s, ev);
+        case 4: return launch_typed<4, S>(a, n_cu, s, ev);
+        case 5: return launch_typed<5, S>(a, n_cu, s, ev);
+        case 6: return launch_typed<6, S>(a, n_cu, s, ev);
+        case 7: return launch_typed<7, S>(a, n_cu, s, ev);
+        case 8: return launch_typed<8, S>(a, n_cu, s, ev);
+        default: return launch_typed<16, S>(a, n_cu, s, ev);
     }
 }
 
-dvl_status launch_update(const UpdArgs& a, int n_cu, hipStream_t s) {
-    if (a.dtype == DVL_F16) return launch_m<F16>(a, n_cu, s);
-    if (a.dtype == DVL_BF16) return launch_m<BF16>(a, n_cu, s);
-    return launch_m<F32>(a, n_cu, s);
+dvl_status launch_update(const UpdArgs& a, int n_cu, hipStream_t s, hipEvent_t* ev) {
+    if (a.dtype == DVL_F16) return launch_m<F16>(a, n_cu, s, ev);
+    if (a.dtype == DVL_BF16) return launch_m<BF16>(a, n_cu, s, ev);
+    return launch_m<F32>(a, n_cu, s, ev);
 }
 
 }  // namespace dvl

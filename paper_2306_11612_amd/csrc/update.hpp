@@ -68,6 +68,9 @@ struct UpdArgs {
     float* vmax_used;
 };
 
-dvl_status launch_update(const UpdArgs& a, int n_cu, hipStream_t s);
+constexpr int kPhases = 5;   // exact vmax, tile sums, carry, bin, edges
+
+// ev (optional): kPhases + 1 events recorded before the first and after every phase
+dvl_status launch_update(const UpdArgs& a, int n_cu, hipStream_t s, hipEvent_t* ev = nullptr);
 
 }  // namespace dvl

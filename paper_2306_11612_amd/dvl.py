@@ -74,6 +74,8 @@ def lib():
         "dvl_read_bins": (i32, [vp, C.POINTER(dvl_bins), i32, vp] + [vp] * 9),
         "dvl_export_order": (i32, [vp, vp, vp, vp]),
         "dvl_export_sorted": (i32, [vp, vp, vp, vp]),
+        "dvl_set_timing": (i32, [vp, i32]),
+        "dvl_kernel_times": (i32, [vp, vp, C.POINTER(i32)]),
         "dvl_num_cells": (i64, [vp]),
         "dvl_num_fields": (i32, [vp]),
         "dvl_grid_bits": (i32, [vp]),
@@ -262,6 +264,19 @@ class Volume:
         _check(lib().dvl_export_sorted(self.handle, _ptr(level), C.cast(arr, C.c_void_p),
                                        _stream_ptr(stream)), "dvl_export_sorted")
         return level, fields
+
+    def set_timing(self, enable: bool = True):
+        """dvl_set_timing: record per-kernel HIP events on every update."""
+        _check(lib().dvl_set_timing(self.handle, 1 if enable else 0), "dvl_set_timing")
+
+    def kernel_times(self):
+        """dvl_kernel_times: ({phase: summed ms}, number of updates), then reset."""
+        ms = np.zeros(5, np.float64)
+        n = C.c_int32()
+        _check(lib().dvl_kernel_times(self.handle, ms.ctypes.data_as(C.c_void_p), C.byref(n)),
+               "dvl_kernel_times")
+        names = ("vmax_exact", "tile_sums", "carry", "bin", "edges")
+        return dict(zip(names, ms.tolist())), int(n.value)
 
     def close(self):
         if self.handle:

@@ -25,6 +25,14 @@ SEED = 230611612
 # sub-stream identifiers
 S_REFINE, S_FIELDS, S_TF, S_REQ, S_SIZES = 1, 2, 3, 4, 5
 
+# optional progress callback (long generations report each stage)
+PROGRESS = None
+
+
+def _progress(msg: str):
+    if PROGRESS is not None:
+        PROGRESS(msg)
+
 
 @dataclass
 class Volume:
@@ -104,6 +112,7 @@ def refine_amr(base: int, refine_fracs, seed: int, device="cpu", octaves: int = 
             thr = torch.kthvalue(v.cpu(), n_cur - n_refine).values.item()
             mask = v > thr
         del v
+        _progress(f"level {lev}: {n_cur} cells, refining {int(mask.sum())}")
         keep = cur[~mask]
         leaves_c.append(keep)
         leaves_l.append(torch.full((keep.shape[0],), lev, dtype=torch.uint8, device=device))
@@ -175,6 +184,7 @@ def make_amr(base: int, refine_fracs, n_fields: int, seed: int, device="cpu",
     width = (1 << level.to(torch.int64))
     cent = (corners.to(torch.float64) + 0.5 * width[:, None].to(torch.float64)) / float(extent)
     del width
+    _progress(f"{corners.shape[0]} leaf cells; evaluating {n_fields} fields")
     fields, names = astro_fields(cent, seed, n_fields, field_octaves)
     del cent
     return Volume(corners[:, 0].int(), corners[:, 1].int(), corners[:, 2].int(), level,

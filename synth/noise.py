@@ -93,12 +93,19 @@ def gradient_noise(p: torch.Tensor, seed: int) -> torch.Tensor:
     return out
 
 
+def _chunk(p: torch.Tensor, chunk: int | None) -> int:
+    if chunk is not None:
+        return chunk
+    return (1 << 25) if p.is_cuda else (1 << 22)
+
+
 def fbm(p: torch.Tensor, seed: int, octaves: int = 6, base_freq: float = 4.0,
-        lacunarity: float = 2.0, gain: float = 0.5, chunk: int = 1 << 22) -> torch.Tensor:
+        lacunarity: float = 2.0, gain: float = 0.5, chunk: int | None = None) -> torch.Tensor:
     """Fractional Brownian motion: sum over octaves of gradient noise, each
     octave with its own seed.  ``p`` is [n, 3] in the unit cube (float64).
     Evaluated in chunks of ``chunk`` points to bound temporary memory."""
     n = p.shape[0]
+    chunk = _chunk(p, chunk)
     out = torch.empty(n, dtype=torch.float64, device=p.device)
     for s in range(0, n, chunk):
         q = p[s:s + chunk]
@@ -122,11 +129,12 @@ def blob_params(seed: int, n_blobs: int = 8):
     return c, sig, amp
 
 
-def blobs(p: torch.Tensor, seed: int, n_blobs: int = 8, chunk: int = 1 << 22) -> torch.Tensor:
+def blobs(p: torch.Tensor, seed: int, n_blobs: int = 8, chunk: int | None = None) -> torch.Tensor:
     """Sum of ``n_blobs`` seeded isotropic Gaussian blobs at points ``p``."""
     c, sig, amp = blob_params(seed, n_blobs)
     c, sig, amp = c.to(p.device), sig.to(p.device), amp.to(p.device)
     n = p.shape[0]
+    chunk = _chunk(p, chunk)
     out = torch.empty(n, dtype=torch.float64, device=p.device)
     for s in range(0, n, chunk):
         q = p[s:s + chunk]
