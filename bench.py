@@ -47,6 +47,34 @@ def make_workload(name: str, base: int | None, device: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources, the build script and the C header (the
+    inputs of libdvl.so); profiles record it next to their counters."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2306_11612_amd", "csrc", "*")))
+    files += [os.path.join(ROOT, "paper_2306_11612_amd", "build.py"), os.path.join(ROOT, "include", "dvl.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload: str, dtype: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None if there is none or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{dtype}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch", {}).get("k_" + kernel)
+
+
 def cpu_baseline(V, alphas, n_bins: int, sample: int, exponent: float, fmin: float):
     """The oracle (single-threaded C, fp64) on the first `sample` sorted cells."""
     import numpy as np
@@ -82,7 +110,20 @@ def main():
     ap.add_argument("--min-importance", type=float, default=0.025)
     ap.add_argument("--cpu-sample", type=int, default=64_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device copy of BYTES bytes (calibrates HBM byte counters)")
     args = ap.parse_args()
+
+    if args.copy_only:
+        import torch
+        n = args.copy_only // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the update shards by "
@@ -151,14 +192,19 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     log(f"{args.steps} steps in {wall:.3f} s: {ms_per_step:.3f} ms/update; kernels {phases}")
 
-    # roofline of the dominant kernel: it streams every cell's level and M fields once
+    # roofline of the dominant kernel (the importance pass): it streams every
+    # cell's level and M fields once.  The projection pass re-reads only tiles
+    # that contain a bin edge (at most min(tiles, W) of them).
     elem = 4 if args.dtype == "f32" else 2
     bytes_per_cell = M * elem + 1
     alg_bytes = n * bytes_per_cell
     per_launch = {k: v / max(n_upd, 1) for k, v in phases.items()}
     dom = max(("tile_sums", "bin"), key=lambda k: per_launch[k])
     achieved = alg_bytes / (per_launch[dom] * 1e-3) / 1e9
-    update_gbps = 2 * alg_bytes / (ms_per_step * 1e-3) / 1e9
+    n_tiles = (n + 4095) // 4096
+    rescan_bytes = min(n_tiles, args.bins) * 4096 * bytes_per_cell
+    update_bytes = alg_bytes + rescan_bytes
+    update_gbps = update_bytes / (ms_per_step * 1e-3) / 1e9
 
     out = {
         "metric": METRIC,
@@ -177,9 +223,11 @@ def main():
                    "field_storage": args.dtype, "n_bins": args.bins, "exponent": args.exponent,
                    "min_importance": args.min_importance, "tf_control_points": 4},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": profiled_traffic(args.workload, args.dtype, dom),
                      "bytes_per_launch": alg_bytes, "bytes_per_cell": bytes_per_cell,
                      "avg_launch_ms": per_launch[dom]},
+        "update_bytes": update_bytes,
         "update_hbm_gbps": update_gbps,
         "update_hbm_frac": update_gbps / HBM_PEAK_GBPS,
         "kernel_ms_per_update": per_launch,

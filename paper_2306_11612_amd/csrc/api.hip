@@ -93,6 +93,10 @@ struct dvl_volume {
     hipEvent_t param_ev[kRing] = {};
     bool param_used[kRing] = {};
     int param_next = 0;
+    // per-tile statistics of the sorted fields: sum [M][T], min [M][T], max [M][T]
+    double* agg_sum = nullptr;
+    float* agg_min = nullptr;
+    float* agg_max = nullptr;
     // update workspace
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -268,6 +272,23 @@ dvl_status dvl_build_order(int64_t n, const int32_t* x, const int32_t* y, const 
         v->fields_s[m] = fb.release();
         v->bytes += (size_t)v->n_pad * eb;
     }
+    {
+        DevBuf as, an, ax;
+        const size_t mt = (size_t)M * v->n_tiles;
+        if (dvl_status st = as.alloc(mt * 8, "tile sums")) return st;
+        if (dvl_status st = an.alloc(mt * 4, "tile minima")) return st;
+        if (dvl_status st = ax.alloc(mt * 4, "tile maxima")) return st;
+        v->agg_sum = (double*)as.release();
+        v->agg_min = (float*)an.release();
+        v->agg_max = (float*)ax.release();
+        v->bytes += mt * 16;
+        for (int m = 0; m < M; ++m)
+            if (dvl_status st = launch_tile_aggregates(n, dtype, v->fields_s[m], v->n_tiles,
+                                                       v->agg_sum + (size_t)m * v->n_tiles,
+                                                       v->agg_min + (size_t)m * v->n_tiles,
+                                                       v->agg_max + (size_t)m * v->n_tiles, v->n_cu, s))
+                return st;
+    }
     DVL_HIP(hipMemcpyAsync(rinit.data(), rng.p, rinit.size() * 4, hipMemcpyDeviceToHost, s));
     DVL_HIP(hipStreamSynchronize(s));
     for (int m = 0; m < M; ++m) {
@@ -320,6 +341,13 @@ dvl_status dvl_set_field(dvl_volume* v, int32_t m, const void* values, void* str
     DVL_HIP(hipMemcpyAsync(rng.p, r, sizeof r, hipMemcpyHostToDevice, s));
     if (dvl_status st = launch_gather(v->n, v->perm, values, v->fields_s[m], eb, s)) { v->sticky = st; return st; }
     if (dvl_status st = launch_range(v->n, v->dtype, v->fields_s[m], (unsigned int*)rng.p, s)) { v->sticky = st; return st; }
+    if (dvl_status st = launch_tile_aggregates(v->n, v->dtype, v->fields_s[m], v->n_tiles,
+                                               v->agg_sum + (size_t)m * v->n_tiles,
+                                               v->agg_min + (size_t)m * v->n_tiles,
+                                               v->agg_max + (size_t)m * v->n_tiles, v->n_cu, s)) {
+        v->sticky = st;
+        return st;
+    }
     DVL_HIP(hipMemcpyAsync(r, rng.p, sizeof r, hipMemcpyDeviceToHost, s));
     DVL_HIP(hipStreamSynchronize(s));
     if (r[2]) return fail(DVL_E_RANGE, "field %d holds a NaN", m);
@@ -389,6 +417,12 @@ dvl_status dvl_update(dvl_volume* v, const dvl_params* p, const dvl_bins* out, v
     UpdArgs a{};
     a.n = v->n;
     a.n_tiles = v->n_tiles;
+    {
+        // runs of consecutive tiles, one per wave of the importance pass
+        const int64_t waves = (int64_t)v->n_cu * 8 * (kUpdThreads / kWave);
+        a.tiles_per_run = std::max<int64_t>(1, (v->n_tiles + waves - 1) / waves);
+        a.n_runs = (v->n_tiles + a.tiles_per_run - 1) / a.tiles_per_run;
+    }
     a.M = v->M;
     a.dtype = v->dtype;
     a.W = p->n_bins;
@@ -441,6 +475,9 @@ dvl_status dvl_update(dvl_volume* v, const dvl_params* p, const dvl_bins* out, v
     a.level = v->level_s;
     for (int m = 0; m < v->M; ++m) a.fields[m] = v->fields_s[m];
     a.ws = v->wsv;
+    a.agg_sum = v->agg_sum;
+    a.agg_min = v->agg_min;
+    a.agg_max = v->agg_max;
     a.first_cell = out->first_cell;
     a.last_cell = out->last_cell;
     a.mean = out->mean;
@@ -561,6 +598,9 @@ void dvl_destroy(dvl_volume* v) {
     if (v->keys_s) (void)hipFree(v->keys_s);
     if (v->perm) (void)hipFree(v->perm);
     if (v->ws) (void)hipFree(v->ws);
+    if (v->agg_sum) (void)hipFree(v->agg_sum);
+    if (v->agg_min) (void)hipFree(v->agg_min);
+    if (v->agg_max) (void)hipFree(v->agg_max);
     for (auto* pool : {&v->ev_pool, &v->ev_pending})
         for (auto& set : *pool)
             for (auto e : set) (void)hipEventDestroy(e);

@@ -3,22 +3,26 @@
 //
 //   K0 k_vmax_exact   (DVL_VMAX_EXACT only) max over cells of V_h
 //   K1 k_tile_sums    TF lookup, V_h (Eq. 1), importance f (Eq. 3) and the
-//                     fp64 sum of f over every 4096-cell wave tile
-//   K2 k_carry        carry[t] = sum of earlier tile sums (Eq. 4 across
-//                     tiles, fp64 or compensated fp32), made monotone
-//   K3 k_bin          recompute f; in-tile monotone prefix; pixel interval
-//                     of every cell; bins complete inside a tile are reduced
-//                     and finalised directly, the tile's first and last bin
-//                     go to per-tile partial records
+//                     fp64 sum of f over every 4096-cell tile; each wave owns
+//                     a run of consecutive tiles and records their prefix
+//                     inside the run
+//   K2 k_carry        exclusive scan of the run totals (Eq. 4 across runs,
+//                     fp64 or compensated fp32), made monotone
+//   K3 k_bin          per tile: if its pixel interval lies inside one bin,
+//                     the tile's precomputed field statistics are its record;
+//                     otherwise recompute f, in-tile monotone prefix, pixel
+//                     interval of every cell; bins complete inside the tile
+//                     are finalised directly, its first and last bin go to
+//                     per-tile partial records
 //   K4 k_edges        merge the partial records of bins shared by tiles in
 //                     tile order; mean, min, max and height y = alpha(mean)
 //
 // The paper's GPU version runs the projection once per field with global
-// atomics on the W bins (its Table 1 bottleneck).  Here all fields are
-// reduced in one pass, atomic-free: a wave owns a contiguous tile, keeps
-// per-lane accumulators while a whole 256-cell step falls in one bin, and
-// switches to a segmented lane scan only at bin boundaries.  Results are
-// bitwise deterministic.
+// atomics on the W bins (its Table 1 bottleneck).  Here the projection is
+// hierarchical over 4096-cell tiles (the paper's future-work suggestion):
+// only tiles that contain a bin edge are read again, all fields at once and
+// atomic-free (per-lane accumulators while a 256-cell step stays in one bin,
+// a per-bin wave reduction at bin edges).  Results are bitwise deterministic.
 #include "update.hpp"
 
 #include <climits>
@@ -31,8 +35,9 @@ static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t workspace_bytes(int64_t T, int M) {
     size_t b = 0;
-    b += al256((size_t)T * 8);             // tile_sum
-    b += al256((size_t)(T + 1) * 8);       // carry
+    b += al256((size_t)T * 8);             // local_prefix
+    b += al256((size_t)T * 8);             // run_total
+    b += al256((size_t)(T + 1) * 8);       // run_base
     b += 2 * al256((size_t)T * 4);         // head/tail bin
     b += 2 * al256((size_t)2 * T * 4);     // rec first/last
     b += al256((size_t)2 * M * T * 8);     // rec_sum
@@ -44,8 +49,9 @@ size_t workspace_bytes(int64_t T, int M) {
 void workspace_carve(void* base, int64_t T, int M, UpdWorkspace* w) {
     char* p = (char*)base;
     auto take = [&](size_t bytes) { char* q = p; p += al256(bytes); return (void*)q; };
-    w->tile_sum = (double*)take((size_t)T * 8);
-    w->carry = (double*)take((size_t)(T + 1) * 8);
+    w->local_prefix = (double*)take((size_t)T * 8);
+    w->run_total = (double*)take((size_t)T * 8);
+    w->run_base = (double*)take((size_t)(T + 1) * 8);
     w->head_bin = (int32_t*)take((size_t)T * 4);
     w->tail_bin = (int32_t*)take((size_t)T * 4);
     w->rec_first = (uint32_t*)take((size_t)2 * T * 4);
@@ -176,6 +182,33 @@ __global__ __launch_bounds__(kUpdThreads) void k_vmax_exact(UpdArgs a) {
 
 // ------------------------------------------------------------------ K1
 
+// running sum of tile sums along a run, in the arithmetic of the scan mode
+struct RunAcc {
+    double d;
+    float hi, lo;
+    __device__ void init() { d = 0.0; hi = 0.0f; lo = 0.0f; }
+    __device__ double value(int mode) const {
+        return mode == DVL_SCAN_FP64 ? d : (mode == DVL_SCAN_KAHAN_FP32 ? (double)hi + (double)lo : (double)hi);
+    }
+    __device__ void add(int mode, double x) {
+        if (mode == DVL_SCAN_FP64) {
+            d += x;
+        } else if (mode == DVL_SCAN_KAHAN_FP32) {
+            const float xf = (float)x;
+            const float s = hi + xf, bb = s - hi;
+            const float e = (hi - (s - bb)) + (xf - bb);
+            const float l = lo + e;
+            hi = s + l;
+            lo = l - (hi - s);
+        } else {
+            hi += (float)x;
+        }
+    }
+};
+
+// Wave r owns the run of consecutive tiles [r k, (r + 1) k): it streams their
+// cells, sums the importance f of every 4096-cell tile in fp64 and records,
+// for every tile, the (non-decreasing) sum of the earlier tiles of its run.
 template <int MT, typename S>
 __global__ __launch_bounds__(kUpdThreads) void k_tile_sums(UpdArgs a) {
     extern __shared__ float tf_lds[];
@@ -183,34 +216,49 @@ __global__ __launch_bounds__(kUpdThreads) void k_tile_sums(UpdArgs a) {
     const int M = fields_of<MT>(a);
     const ImpCtx c = make_ctx(a);
     const int lane = lane_id();
-    const int64_t wave = (int64_t)blockIdx.x * (kUpdThreads / kWave) + threadIdx.x / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * (kUpdThreads / kWave);
-    for (int64_t t = wave; t < a.n_tiles; t += nwaves) {
-        double acc = 0.0;
-        const int64_t tbase = t * kTileCells;
-        const int nsteps = (int)min((int64_t)kTileSteps, (a.n - tbase + kStepCells - 1) / kStepCells);
-        StepData<MT, S> cur;
-        cur.load(a, M, (tbase >> 2) + lane);
-        for (int s = 0; s < nsteps; ++s) {
-            const int64_t quad = ((tbase + (int64_t)s * kStepCells) >> 2) + lane;
-            StepData<MT, S> nxt;
-            if (s + 1 < nsteps) nxt.load(a, M, quad + kWave);
-            float f[4];
+    const int64_t r = (int64_t)blockIdx.x * (kUpdThreads / kWave) + threadIdx.x / kWave;
+    if (r >= a.n_runs) return;
+    const int64_t t_begin = r * a.tiles_per_run;
+    const int64_t t_end = min(a.n_tiles, t_begin + a.tiles_per_run);
+    const int64_t c_begin = t_begin * kTileCells;
+    const int64_t c_end = min(a.n, t_end * kTileCells);
+    const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
+
+    RunAcc run;
+    run.init();
+    double prev = 0.0;
+    double tacc = 0.0;
+    int64_t t = t_begin;
+    int in_tile = 0;
+    StepData<MT, S> cur;
+    cur.load(a, M, (c_begin >> 2) + lane);
+    for (int s = 0; s < nsteps; ++s) {
+        const int64_t quad = ((c_begin + (int64_t)s * kStepCells) >> 2) + lane;
+        StepData<MT, S> nxt;
+        if (s + 1 < nsteps) nxt.load(a, M, quad + kWave);
+        float f[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                float x[MT];
+        for (int k = 0; k < 4; ++k) {
+            float x[MT];
 #pragma unroll
-                for (int m = 0; m < MT; ++m) x[m] = m < M ? cur.q[m].get(k) : 0.0f;
-                const float v = variation<MT>(x, M, tf_lds, a, c);
-                const float fk = importance_from_v(v, (cur.lv >> (8 * k)) & 0xFFu, c);
-                f[k] = ((quad << 2) + k < a.n) ? fk : 0.0f;
-            }
-            acc += (double)((f[0] + f[1]) + (f[2] + f[3]));
-            cur = nxt;
+            for (int m = 0; m < MT; ++m) x[m] = m < M ? cur.q[m].get(k) : 0.0f;
+            const float v = variation<MT>(x, M, tf_lds, a, c);
+            const float fk = importance_from_v(v, (cur.lv >> (8 * k)) & 0xFFu, c);
+            f[k] = ((quad << 2) + k < a.n) ? fk : 0.0f;
         }
-        acc = wave_sum_d(acc);
-        if (lane == 0) a.ws.tile_sum[t] = acc;
+        tacc += (double)((f[0] + f[1]) + (f[2] + f[3]));
+        if (++in_tile == kTileSteps || s + 1 == nsteps) {
+            const double ts = wave_sum_d(tacc);
+            tacc = 0.0;
+            prev = fmax(prev, run.value(a.scan_mode));
+            if (lane == 0) a.ws.local_prefix[t] = prev;
+            run.add(a.scan_mode, ts);
+            ++t;
+            in_tile = 0;
+        }
+        cur = nxt;
     }
+    if (lane == 0) a.ws.run_total[r] = fmax(prev, run.value(a.scan_mode));
 }
 
 // ------------------------------------------------------------------ K2
@@ -221,6 +269,8 @@ struct AccF64 {
     __device__ void add(double x) { v += x; }
     __device__ static AccF64 combine(const AccF64& a, const AccF64& b) { return {a.v + b.v}; }
     __device__ double value() const { return v; }
+    __device__ AccF64 shfl_up(int d) const { return {shfl_up_d(v, d)}; }
+    __device__ AccF64 lane(int l) const { return {readlane(v, l)}; }
 };
 
 // compensated fp32: unevaluated sum hi + lo, error-free TwoSum on every add
@@ -248,6 +298,8 @@ struct AccKahan32 {
         return r;
     }
     __device__ double value() const { return (double)hi + (double)lo; }
+    __device__ AccKahan32 shfl_up(int d) const { return {shfl_up_f(hi, d), shfl_up_f(lo, d)}; }
+    __device__ AccKahan32 lane(int l) const { return {readlane(hi, l), readlane(lo, l)}; }
 };
 
 struct AccF32 {
@@ -256,75 +308,103 @@ struct AccF32 {
     __device__ void add(double x) { v += (float)x; }
     __device__ static AccF32 combine(const AccF32& a, const AccF32& b) { return {a.v + b.v}; }
     __device__ double value() const { return (double)v; }
+    __device__ AccF32 shfl_up(int d) const { return {shfl_up_f(v, d)}; }
+    __device__ AccF32 lane(int l) const { return {readlane(v, l)}; }
 };
 
 constexpr int kCarryThreads = 1024;
+constexpr int kCarryItems = 8;                              // run totals per thread and round
+constexpr int kCarryRound = kCarryThreads * kCarryItems;
+constexpr int kCarryWaves = kCarryThreads / kWave;
 
+// run_base[r] = sum of the run totals before r, run_base[R] = F_tot.  One
+// workgroup walks the run totals in rounds of 8192: a sequential prefix over
+// each thread's 8 values, a wave scan of the thread totals made monotone by a
+// running maximum, and sequential wave and round bases; every base is clamped
+// to the next thread's base, so the bases never decrease.
 template <typename Acc>
 __global__ __launch_bounds__(kCarryThreads) void k_carry(UpdArgs a) {
-    __shared__ Acc sh[kCarryThreads];
-    __shared__ double shm[kCarryThreads];
-    const int64_t T = a.n_tiles;
-    const int tid = threadIdx.x;
-    const double* ts = a.ws.tile_sum;
-    double* carry = a.ws.carry;
-
-    // 1. every thread sums its contiguous chunk of tile sums
-    const int64_t chunk = (T + kCarryThreads - 1) / kCarryThreads;
-    const int64_t lo = min(T, (int64_t)tid * chunk), hi = min(T, lo + chunk);
-    Acc s = Acc::zero();
-    for (int64_t i = lo; i < hi; ++i) s.add(ts[i]);
-
-    // 2. inclusive Hillis-Steele scan of the chunk totals across the block
-    sh[tid] = s;
-    __syncthreads();
-    for (int d = 1; d < kCarryThreads; d <<= 1) {
-        Acc v = sh[tid];
-        if (tid >= d) v = Acc::combine(sh[tid - d], v);
-        __syncthreads();
-        sh[tid] = v;
-        __syncthreads();
-    }
-    Acc run = tid == 0 ? Acc::zero() : sh[tid - 1];
-
-    // 3. sequential carries inside the chunk; carry[T] is the total
-    for (int64_t i = lo; i < hi; ++i) {
-        carry[i] = run.value();
-        run.add(ts[i]);
-    }
-    if (tid == kCarryThreads - 1) carry[T] = sh[kCarryThreads - 1].value();
-    __syncthreads();
-
-    // 4. make the carries monotone (rounding of the block scan can step back
-    //    by an ulp at chunk boundaries): running maximum over carry[0..T]
-    const int64_t n1 = T + 1;
-    const int64_t ch1 = (n1 + kCarryThreads - 1) / kCarryThreads;
-    const int64_t lo1 = min(n1, (int64_t)tid * ch1), hi1 = min(n1, lo1 + ch1);
-    double m = 0.0;
-    for (int64_t i = lo1; i < hi1; ++i) m = fmax(m, carry[i]);
-    shm[tid] = m;
-    __syncthreads();
-    for (int d = 1; d < kCarryThreads; d <<= 1) {
-        double v = shm[tid];
-        if (tid >= d) v = fmax(shm[tid - d], v);
-        __syncthreads();
-        shm[tid] = v;
-        __syncthreads();
-    }
-    double rm = tid == 0 ? 0.0 : shm[tid - 1];
-    for (int64_t i = lo1; i < hi1; ++i) {
-        rm = fmax(rm, carry[i]);
-        carry[i] = rm;
+    __shared__ double wave_base[kCarryWaves + 1];
+    __shared__ Acc wave_acc[kCarryWaves];
+    __shared__ Acc round_acc;
+    __shared__ double round_end;
+    const int64_t T = a.n_runs;
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const double* ts = a.ws.run_total;
+    double* carry = a.ws.run_base;
+    if (tid == 0) {
+        round_acc = Acc::zero();
+        round_end = 0.0;
     }
     __syncthreads();
 
-    // 5. total; a zero total means every f was zero: fall back to f = 1
+    for (int64_t r0 = 0; r0 < T; r0 += kCarryRound) {
+        const int64_t b0 = r0 + (int64_t)tid * kCarryItems;
+        double v[kCarryItems];
+#pragma unroll
+        for (int k = 0; k < kCarryItems; ++k) v[k] = (b0 + k < T) ? ts[b0 + k] : 0.0;
+        // thread-sequential prefix in the chosen arithmetic
+        Acc pre[kCarryItems];
+        Acc run = Acc::zero();
+#pragma unroll
+        for (int k = 0; k < kCarryItems; ++k) {
+            pre[k] = run;
+            run.add(v[k]);
+        }
+        // inclusive wave scan of the thread totals
+        Acc inc = run;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const Acc o = inc.shfl_up(d);
+            if (lane >= d) inc = Acc::combine(o, inc);
+        }
+        if (lane == kWave - 1) wave_acc[w] = inc;
+        __syncthreads();
+        if (tid == 0) {
+            // sequential over the waves: non-decreasing wave bases
+            Acc base = round_acc;
+            double prev = round_end;
+            for (int q = 0; q < kCarryWaves; ++q) {
+                prev = fmax(prev, base.value());
+                wave_base[q] = prev;
+                base = Acc::combine(base, wave_acc[q]);
+            }
+            prev = fmax(prev, base.value());
+            wave_base[kCarryWaves] = prev;
+            round_end = prev;
+            round_acc = base;
+        }
+        __syncthreads();
+        // thread base = wave base + exclusive wave prefix, kept inside the
+        // wave's range and made non-decreasing by a running maximum
+        const double wb = wave_base[w], wn = wave_base[w + 1];
+        const Acc exc = inc.shfl_up(1);
+        double tb = lane == 0 ? wb : fmin(fmax(wb + exc.value(), wb), wn);
+        for (int d = 1; d < kWave; d <<= 1) {
+            const double o = shfl_up_d(tb, d);
+            if (lane >= d) tb = fmax(tb, o);
+        }
+        // the next thread's base bounds this thread's carries
+        const int src = lane + 1 < kWave ? lane + 1 : lane;
+        const uint64_t u = __double_as_longlong(tb);
+        const int nlo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)u);
+        const int nhi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(u >> 32));
+        double nb = __longlong_as_double(((uint64_t)(uint32_t)nhi << 32) | (uint32_t)nlo);
+        if (lane == kWave - 1) nb = wn;
+        double c = tb;
+#pragma unroll
+        for (int k = 0; k < kCarryItems; ++k) {
+            c = fmax(c, fmin(tb + pre[k].value(), nb));
+            if (b0 + k < T) carry[b0 + k] = c;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) carry[T] = round_end;
+    __syncthreads();
+
+    // a zero total means every f was zero: fall back to f = 1 (linear map;
+    // the projection then derives the tile offsets from the cell counts)
     const double F = carry[T];
     const bool degenerate = !(F > 0.0);
-    if (degenerate) {
-        for (int64_t i = tid; i < T; i += kCarryThreads) carry[i] = (double)(i * kTileCells);
-        if (tid == 0) carry[T] = (double)a.n;
-    }
     if (tid == 0) {
         a.ws.scal[0] = degenerate ? (double)a.n : F;
         a.ws.scal[1] = degenerate ? 1.0 : 0.0;
@@ -354,29 +434,6 @@ __device__ __forceinline__ void seg_clear(Seg<MT>& s) {
     s.last = 0u;
 }
 
-template <int MT>
-__device__ __forceinline__ void seg_init(Seg<MT>& s, const float (&x)[MT], uint32_t g) {
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        s.sum[m] = (double)x[m];
-        s.mn[m] = x[m];
-        s.mx[m] = x[m];
-    }
-    s.first = g;
-    s.last = g;
-}
-
-template <int MT>
-__device__ __forceinline__ void seg_add(Seg<MT>& s, const float (&x)[MT], uint32_t g) {
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        s.sum[m] += (double)x[m];
-        s.mn[m] = fminf(s.mn[m], x[m]);
-        s.mx[m] = fmaxf(s.mx[m], x[m]);
-    }
-    s.last = g;
-}
-
 // a precedes b in cell order
 template <int MT>
 __device__ __forceinline__ Seg<MT> seg_combine(const Seg<MT>& a, const Seg<MT>& b) {
@@ -392,78 +449,147 @@ __device__ __forceinline__ Seg<MT> seg_combine(const Seg<MT>& a, const Seg<MT>& 
     return r;
 }
 
-template <int MT>
-__device__ __forceinline__ Seg<MT> seg_shfl_up(const Seg<MT>& s, int d) {
-    Seg<MT> r;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        r.sum[m] = shfl_up_d(s.sum[m], d);
-        r.mn[m] = shfl_up_f(s.mn[m], d);
-        r.mx[m] = shfl_up_f(s.mx[m], d);
-    }
-    r.first = (uint32_t)shfl_up_i((int)s.first, d);
-    r.last = (uint32_t)shfl_up_i((int)s.last, d);
-    return r;
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ o) << 2, (int)v));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ o) << 2, (int)v));
+    return v;
+}
+__device__ __forceinline__ int wave_min_i32(int v) {
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, __builtin_amdgcn_ds_bpermute((lane_id() ^ o) << 2, v));
+    return v;
 }
 
-template <int MT>
-__device__ __forceinline__ Seg<MT> seg_readlane(const Seg<MT>& s, int l) {
-    Seg<MT> r;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        r.sum[m] = readlane(s.sum[m], l);
-        r.mn[m] = readlane(s.mn[m], l);
-        r.mx[m] = readlane(s.mx[m], l);
-    }
-    r.first = readlane(s.first, l);
-    r.last = readlane(s.last, l);
-    return r;
+
+// Sum of the importance of all tiles before tile t (t = T gives F_tot): the
+// run's base plus the tile's prefix inside its run, never above the next
+// run's base.  One definition serves both neighbours of every tile boundary,
+// and the offsets never decrease.
+__device__ __forceinline__ double tile_offset(const UpdArgs& a, int64_t t, bool degenerate) {
+    if (degenerate) return t >= a.n_tiles ? (double)a.n : (double)(t * kTileCells);
+    if (t >= a.n_tiles) return a.ws.run_base[a.n_runs];
+    const int64_t r = t / a.tiles_per_run;
+    const double lo = a.ws.run_base[r], hi = a.ws.run_base[r + 1];
+    return fmin(fmax(lo + a.ws.local_prefix[t], lo), hi);
 }
 
-// a bin whose cells all lie in this tile: finalise it
+// Per-wave LDS scratch of the bin reductions: the partial statistics of up to
+// kRedFields fields for the 64 lanes, then the reduced values.
+constexpr int kRedFields = 4;
+struct RedScratch {
+    double sum[kRedFields][kWave];
+    float mn[kRedFields][kWave];
+    float mx[kRedFields][kWave];
+    double rsum[kRedFields];
+    float rmn[kRedFields];
+    float rmx[kRedFields];
+};
+constexpr size_t kRedBytes = sizeof(RedScratch);
+
+// Reduce the per-lane partials (asum, amin, amax) of one bin over the wave
+// and store the bin: a complete bin (dest 0) gets its final mean, min, max
+// and height; a tile-edge bin goes to the tile's head (dest 1) or tail
+// (dest 2) record.  Fields are taken kRedFields at a time; lane j < 3 * F
+// reduces one column in lane order, lanes m < F finalise field m.
 template <int MT>
-__device__ void write_final(const UpdArgs& a, int M, int key, const Seg<MT>& s, const float* tf) {
-    const uint32_t cnt = s.last - s.first + 1u;
-    a.first_cell[key] = s.first;
-    a.last_cell[key] = s.last;
+__device__ void close_bin(const UpdArgs& a, int M, RedScratch* rs, int dest, int64_t t, int key,
+                          uint32_t first, uint32_t last, const double (&asum)[MT],
+                          const float (&amin)[MT], const float (&amax)[MT], const float* tf) {
+    const int lane = lane_id();
+    const uint32_t cnt = last - first + 1u;
+    const int64_t T = a.n_tiles;
+#pragma unroll
+    for (int m0 = 0; m0 < MT; m0 += kRedFields) {
+        if (m0 >= M) break;
+#pragma unroll
+        for (int j = 0; j < kRedFields; ++j) {
+            if (m0 + j < MT) {
+                rs->sum[j][lane] = asum[m0 + j];
+                rs->mn[j][lane] = amin[m0 + j];
+                rs->mx[j][lane] = amax[m0 + j];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int nf = min(kRedFields, M - m0);
+        if (lane < nf) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            for (int l = 0; l < kWave; l += 4) {
+                s0 += rs->sum[lane][l];
+                s1 += rs->sum[lane][l + 1];
+                s2 += rs->sum[lane][l + 2];
+                s3 += rs->sum[lane][l + 3];
+            }
+            rs->rsum[lane] = (s0 + s1) + (s2 + s3);
+        } else if (lane >= 16 && lane < 16 + nf) {
+            const int j = lane - 16;
+            float v = INFINITY;
+            for (int l = 0; l < kWave; ++l) v = fminf(v, rs->mn[j][l]);
+            rs->rmn[j] = v;
+        } else if (lane >= 32 && lane < 32 + nf) {
+            const int j = lane - 32;
+            float v = -INFINITY;
+            for (int l = 0; l < kWave; ++l) v = fmaxf(v, rs->mx[j][l]);
+            rs->rmx[j] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < nf) {
+            const int m = m0 + lane;
+            const double sm = rs->rsum[lane];
+            const float mn = rs->rmn[lane], mx = rs->rmx[lane];
+            if (dest == 0) {
+                const float mean = (float)(sm / (double)cnt);
+                const int e = tf_entry(mean, a.s[m], a.b[m], a.nmax[m]);
+                const int64_t o = (int64_t)m * a.W + key;
+                a.mean[o] = mean;
+                a.vmin[o] = mn;
+                a.vmax[o] = mx;
+                a.y[o] = tf[a.tf_off[m] + e];
+            } else {
+                const int64_t o = ((int64_t)(dest - 1) * M + m) * T + t;
+                a.ws.rec_sum[o] = sm;
+                a.ws.rec_min[o] = mn;
+                a.ws.rec_max[o] = mx;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0) {
+        if (dest == 0) {
+            a.first_cell[key] = first;
+            a.last_cell[key] = last;
+        } else {
+            a.ws.rec_first[(dest - 1) * T + t] = first;
+            a.ws.rec_last[(dest - 1) * T + t] = last;
+        }
+    }
+}
+
+// a bin that holds one cell only (strictly inside a wide cell)
+template <int MT>
+__device__ void write_single(const UpdArgs& a, int M, int key, const float (&x)[MT], uint32_t g,
+                             const float* tf) {
+    a.first_cell[key] = g;
+    a.last_cell[key] = g;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         if (m < M) {
-            const float mean = (float)(s.sum[m] / (double)cnt);
-            const int e = tf_entry(mean, a.s[m], a.b[m], a.nmax[m]);
+            const int e = tf_entry(x[m], a.s[m], a.b[m], a.nmax[m]);
             const int64_t o = (int64_t)m * a.W + key;
-            a.mean[o] = mean;
-            a.vmin[o] = s.mn[m];
-            a.vmax[o] = s.mx[m];
+            a.mean[o] = x[m];
+            a.vmin[o] = x[m];
+            a.vmax[o] = x[m];
             a.y[o] = tf[a.tf_off[m] + e];
         }
     }
-}
-
-// r = 0: head record (the tile's first bin), r = 1: tail record (its last bin)
-template <int MT>
-__device__ void write_record(const UpdArgs& a, int M, int64_t t, int r, const Seg<MT>& s) {
-    const int64_t T = a.n_tiles;
-    a.ws.rec_first[r * T + t] = s.first;
-    a.ws.rec_last[r * T + t] = s.last;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        if (m < M) {
-            const int64_t o = ((int64_t)r * M + m) * T + t;
-            a.ws.rec_sum[o] = s.sum[m];
-            a.ws.rec_min[o] = s.mn[m];
-            a.ws.rec_max[o] = s.mx[m];
-        }
-    }
-}
-
-template <int MT>
-__device__ __forceinline__ void emit_bin(const UpdArgs& a, int M, int64_t t, int Bh, int key,
-                                         const Seg<MT>& s, const float* tf) {
-    if (key == Bh)
-        write_record<MT>(a, M, t, 0, s);
-    else
-        write_final<MT>(a, M, key, s, tf);
 }
 
 // ------------------------------------------------------------------ K3
@@ -472,6 +598,9 @@ template <int MT, typename S>
 __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
     extern __shared__ float tf_lds[];
     load_tf(tf_lds, a.tf, a.tf_total);
+    RedScratch* rs = reinterpret_cast<RedScratch*>(
+        reinterpret_cast<char*>(tf_lds) + ((size_t)a.tf_total * sizeof(float) + 15) / 16 * 16) +
+        threadIdx.x / kWave;
     const int M = fields_of<MT>(a);
     const ImpCtx c = make_ctx(a);
     const bool degenerate = a.ws.scal[1] != 0.0;
@@ -485,18 +614,38 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
 
     for (int64_t t = wave; t < a.n_tiles; t += nwaves) {
         const int64_t tbase = t * kTileCells;
-        const float X0 = (float)(a.ws.carry[t] * scale_d);
-        const float X1 = (float)(a.ws.carry[t + 1] * scale_d);
+        const float X0 = (float)(tile_offset(a, t, degenerate) * scale_d);
+        const float X1 = (float)(tile_offset(a, t + 1, degenerate) * scale_d);
         const int64_t tend = min(tbase + (int64_t)kTileCells, a.n);
         const uint32_t last_valid = (uint32_t)(tend - 1);
         const int nsteps = (int)((tend - tbase + kStepCells - 1) / kStepCells);
+
+        // A tile whose pixel interval [X0, X1] lies inside one bin puts every
+        // cell in that bin: its record is the tile's precomputed statistics and
+        // no cell needs to be read (the projection is hierarchical over tiles).
+        const int b0 = max(0, min((int)floorf(X0), W1));
+        const int b1 = max(0, min((int)floorf(X1), W1));
+        if (b0 == b1) {
+            if (lane < M) {
+                const int64_t src = (int64_t)lane * a.n_tiles + t;
+                const int64_t dst = (int64_t)lane * a.n_tiles + t;   // head record
+                a.ws.rec_sum[dst] = a.agg_sum[src];
+                a.ws.rec_min[dst] = a.agg_min[src];
+                a.ws.rec_max[dst] = a.agg_max[src];
+            }
+            if (lane == 0) {
+                a.ws.rec_first[t] = (uint32_t)tbase;
+                a.ws.rec_last[t] = last_valid;
+                a.ws.head_bin[t] = b0;
+                a.ws.tail_bin[t] = b0;
+            }
+            continue;
+        }
 
         float run = 0.0f;
         bool o_valid = false;
         int O = -1, Bh = -1;
         uint32_t O_first = 0, O_last = 0;
-        Seg<MT> Ob;
-        seg_clear(Ob);
         double asum[MT];
         float amin[MT], amax[MT];
 #pragma unroll
@@ -568,7 +717,6 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
                     o_valid = true;
                     O = key0;
                     O_first = (uint32_t)c0;
-                    seg_clear(Ob);
                 }
                 O_last = (uint32_t)(c0 + kStepCells - 1);
 #pragma unroll
@@ -584,131 +732,99 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
                 continue;
             }
 
-            // ---- bin boundary inside the step: segmented reduction ----
-            // (1) the open bin's statistics so far, uniform across the wave
-            Seg<MT> Os;
-            seg_clear(Os);
-            if (o_valid) {
-#pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    Os.sum[m] = Ob.sum[m] + wave_sum_d(asum[m]);
-                    Os.mn[m] = fminf(Ob.mn[m], wave_min_f(amin[m]));
-                    Os.mx[m] = fmaxf(Ob.mx[m], wave_max_f(amax[m]));
-                    asum[m] = 0.0;
-                    amin[m] = INFINITY;
-                    amax[m] = -INFINITY;
-                }
-                Os.first = O_first;
-                Os.last = O_last;
+            // ---- bin boundary inside the step ----
+            const int last_lane = full ? kWave - 1 : (int)((a.n - 1 - c0) >> 2);
+            const int kl = (int)((a.n - 1 - c0) & 3);
+            const int bhi_last = kl == 0 ? bhi[0] : (kl == 1 ? bhi[1] : (kl == 2 ? bhi[2] : bhi[3]));
+            const int key_last = full ? key_end : readlane(bhi_last, last_lane);
+            // (1) the open bin ended with the previous step: reduce and emit it
+            if (o_valid && key0 != O) {
+                close_bin<MT>(a, M, rs, O == Bh ? 1 : 0, t, O, O_first, O_last, asum, amin, amax, tf_lds);
+                o_valid = false;
             }
-
-            // (2) lane-local pass over this lane's elements: every cell
-            //     belongs to its first bin; a cell spanning bins is also the
-            //     whole content of the bins strictly inside its interval and
-            //     the first member of its last bin
-            bool any = false, hcl = false;
-            int ck = INT_MAX, hk = INT_MAX;
-            Seg<MT> cs, hs;
-            seg_clear(cs);
-            seg_clear(hs);
+            // (2) bins strictly inside a wide cell hold that cell alone
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (!valid[k]) continue;
-                float xk[MT];
+                if (valid[k] && bhi[k] > blo[k] + 1) {
+                    float xk[MT];
 #pragma unroll
-                for (int m = 0; m < MT; ++m) xk[m] = x[m][k];
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    if (e == 1 && bhi[k] == blo[k]) break;
-                    const int key = e == 0 ? blo[k] : bhi[k];
-                    if (e == 1) {
-                        for (int b = blo[k] + 1; b < bhi[k]; ++b) {
-                            Seg<MT> one;
-                            seg_init(one, xk, g[k]);
-                            write_final<MT>(a, M, b, one, tf_lds);
-                        }
-                    }
-                    if (!any) {
-                        any = true;
-                        ck = key;
-                        seg_init(cs, xk, g[k]);
-                    } else if (key == ck) {
-                        seg_add(cs, xk, g[k]);
-                    } else {
-                        if (!hcl) {
-                            hcl = true;
-                            hk = ck;
-                            hs = cs;
-                        } else {
-                            emit_bin<MT>(a, M, t, Bh, ck, cs, tf_lds);  // complete, inside the lane
-                        }
-                        ck = key;
-                        seg_init(cs, xk, g[k]);
-                    }
+                    for (int m = 0; m < MT; ++m) xk[m] = x[m][k];
+                    for (int b = blo[k] + 1; b < bhi[k]; ++b) write_single<MT>(a, M, b, xk, g[k], tf_lds);
                 }
             }
-
-            // (3) segmented inclusive scan of the lanes' last segments
-            const int prev_ck = shfl_up_i(ck, 1);
-            const int prev_any = shfl_up_i(any ? 1 : 0, 1);
-            bool fl = (lane == 0) || hcl || !any || !prev_any || prev_ck != ck;
-            Seg<MT> v = cs;
-            for (int d = 1; d < kWave; d <<= 1) {
-                const Seg<MT> pv = seg_shfl_up(v, d);
-                const bool pf = shfl_up_i(fl ? 1 : 0, d) != 0;
-                if (lane >= d && !fl) {
-                    v = seg_combine(pv, v);
-                    fl = pf;
+            // (3) every bin that is the first or last bin of some cell of this
+            //     step, in increasing order; all but the step's last one close
+            int b = key0;
+            while (true) {
+                // this lane's cells in bin b (first or last bin of the cell)
+                bool in[4];
+                uint32_t gmin = 0xFFFFFFFFu, gmax = 0u;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    in[k] = valid[k] && (blo[k] == b || bhi[k] == b);
+                    if (in[k]) {
+                        gmin = min(gmin, g[k]);
+                        gmax = max(gmax, g[k]);
+                    }
                 }
+                const bool cont = o_valid && b == O;   // continues the open bin
+                if (!cont) {
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+                        asum[m] = 0.0;
+                        amin[m] = INFINITY;
+                        amax[m] = -INFINITY;
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    if (m < M) {
+                        float s4 = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (in[k]) {
+                                s4 += x[m][k];
+                                amin[m] = fminf(amin[m], x[m][k]);
+                                amax[m] = fmaxf(amax[m], x[m][k]);
+                            }
+                        }
+                        asum[m] += (double)s4;
+                    }
+                }
+                const uint32_t bfirst = cont ? O_first : wave_min_u32(gmin);
+                if (b == key_last) {
+                    // stays open into the next step (per-lane accumulators keep it)
+                    O = b;
+                    O_first = bfirst;
+                    O_last = (uint32_t)min((int64_t)c0 + kStepCells - 1, a.n - 1);
+                    o_valid = true;
+                    break;
+                }
+                close_bin<MT>(a, M, rs, b == Bh ? 1 : 0, t, b, bfirst, wave_max_u32(gmax), asum, amin, amax,
+                              tf_lds);
+                o_valid = false;
+                // next key of this step above b
+                int nk = INT_MAX;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (valid[k]) {
+                        if (blo[k] > b) nk = min(nk, blo[k]);
+                        if (bhi[k] > b) nk = min(nk, bhi[k]);
+                    }
+                }
+                b = wave_min_i32(nk);
+                if (b == INT_MAX) break;   // cannot happen: key_last is above
             }
-            const bool o_cont = o_valid && key0 == O;
-            const int last_lane = full ? kWave - 1 : (int)((a.n - 1 - c0) >> 2);
-
-            // (4a) first segments that close inside a lane
-            const Seg<MT> pvs = seg_shfl_up(v, 1);
-            if (hcl) {
-                Seg<MT> agg = hs;
-                if (lane > 0 && prev_any && prev_ck == hk) agg = seg_combine(pvs, hs);
-                if (o_cont && hk == key0) agg = seg_combine(Os, agg);
-                emit_bin<MT>(a, M, t, Bh, hk, agg, tf_lds);
-            }
-            // (4b) last segments that end with this lane (not the last valid lane)
-            const int fk = any ? (hcl ? hk : ck) : INT_MAX;
-            const int next_fk = __builtin_amdgcn_ds_bpermute(min(lane + 1, kWave - 1) << 2, fk);
-            if (any && lane != last_lane && next_fk != ck) {
-                Seg<MT> agg = v;
-                if (o_cont && ck == key0) agg = seg_combine(Os, agg);
-                emit_bin<MT>(a, M, t, Bh, ck, agg, tf_lds);
-            }
-            // (4c) the open bin ended with the previous step
-            if (o_valid && !o_cont && lane == 0) emit_bin<MT>(a, M, t, Bh, O, Os, tf_lds);
-
-            // (5) the last valid lane's segment stays open
-            const int newO = readlane(ck, last_lane);
-            Seg<MT> nv = seg_readlane(v, last_lane);
-            if (o_cont && newO == key0) nv = seg_combine(Os, nv);
-            O = newO;
-            Ob = nv;
-            O_first = nv.first;
-            O_last = nv.last;
-            o_valid = true;
             cur = nxt;
         }
 
         // tile end: the open bin is the tile's last bin
-        Seg<MT> Os;
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            Os.sum[m] = Ob.sum[m] + wave_sum_d(asum[m]);
-            Os.mn[m] = fminf(Ob.mn[m], wave_min_f(amin[m]));
-            Os.mx[m] = fmaxf(Ob.mx[m], wave_max_f(amax[m]));
-        }
-        Os.first = O_first;
-        Os.last = O_last;
-        if (lane == 0 && O >= 0) {
-            write_record<MT>(a, M, t, O == Bh ? 0 : 1, Os);
-            a.ws.head_bin[t] = Bh;
-            a.ws.tail_bin[t] = O;
+        if (o_valid) {
+            close_bin<MT>(a, M, rs, O == Bh ? 1 : 2, t, O, O_first, O_last, asum, amin, amax, tf_lds);
+            if (lane == 0) {
+                a.ws.head_bin[t] = Bh;
+                a.ws.tail_bin[t] = O;
+            }
         }
     }
 }
@@ -805,6 +921,63 @@ __global__ __launch_bounds__(256) void k_edges(UpdArgs a) {
     }
 }
 
+
+// ------------------------------------------------------------------ per-tile statistics
+
+// sum / min / max of one sorted field over every 4096-cell tile; one wave per
+// tile (computed once per volume and per data change, not per update)
+template <typename S>
+__global__ __launch_bounds__(kUpdThreads) void k_tile_aggregates(int64_t n, const void* __restrict__ field,
+                                                                 int64_t n_tiles, double* __restrict__ sum,
+                                                                 float* __restrict__ mn, float* __restrict__ mx) {
+    const int lane = lane_id();
+    const int64_t wave = (int64_t)blockIdx.x * (kUpdThreads / kWave) + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * (kUpdThreads / kWave);
+    for (int64_t t = wave; t < n_tiles; t += nwaves) {
+        const int64_t tbase = t * kTileCells;
+        double acc = 0.0;
+        float lo = INFINITY, hi = -INFINITY;
+        for (int st = 0; st < kTileSteps; ++st) {
+            const int64_t quad = ((tbase + (int64_t)st * kStepCells) >> 2) + lane;
+            Quad<S> q;
+            q.load(field, quad);
+            float s4 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((quad << 2) + k < n) {
+                    const float v = q.get(k);
+                    s4 += v;
+                    lo = fminf(lo, v);
+                    hi = fmaxf(hi, v);
+                }
+            }
+            acc += (double)s4;
+        }
+        acc = wave_sum_d(acc);
+        lo = wave_min_f(lo);
+        hi = wave_max_f(hi);
+        if (lane == 0) {
+            sum[t] = acc;
+            mn[t] = lo;
+            mx[t] = hi;
+        }
+    }
+}
+
+dvl_status launch_tile_aggregates(int64_t n, int dtype, const void* field, int64_t n_tiles, double* sum,
+                                  float* mn, float* mx, int n_cu, hipStream_t s) {
+    const int64_t wg_needed = (n_tiles + (kUpdThreads / kWave) - 1) / (kUpdThreads / kWave);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(wg_needed, (int64_t)n_cu * 8));
+    if (dtype == DVL_F16)
+        hipLaunchKernelGGL(k_tile_aggregates<F16>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles, sum, mn, mx);
+    else if (dtype == DVL_BF16)
+        hipLaunchKernelGGL(k_tile_aggregates<BF16>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles, sum, mn, mx);
+    else
+        hipLaunchKernelGGL(k_tile_aggregates<F32>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles, sum, mn, mx);
+    DVL_HIP(hipGetLastError());
+    return DVL_OK;
+}
+
 // ------------------------------------------------------------------ launcher
 
 template <int MT, typename S>
@@ -822,7 +995,8 @@ static dvl_status launch_typed(const UpdArgs& a, int n_cu, hipStream_t s, hipEve
         DVL_HIP(hipGetLastError());
     }
     if (dvl_status st = mark(1)) return st;
-    hipLaunchKernelGGL((k_tile_sums<MT, S>), dim3(grid), dim3(kUpdThreads), lds, s, a);
+    const unsigned grid_runs = (unsigned)std::max<int64_t>(1, (a.n_runs + (kUpdThreads / kWave) - 1) / (kUpdThreads / kWave));
+    hipLaunchKernelGGL((k_tile_sums<MT, S>), dim3(grid_runs), dim3(kUpdThreads), lds, s, a);
     DVL_HIP(hipGetLastError());
     if (dvl_status st = mark(2)) return st;
     if (a.scan_mode == DVL_SCAN_KAHAN_FP32)
@@ -833,7 +1007,8 @@ static dvl_status launch_typed(const UpdArgs& a, int n_cu, hipStream_t s, hipEve
         hipLaunchKernelGGL(k_carry<AccF64>, dim3(1), dim3(kCarryThreads), 0, s, a);
     DVL_HIP(hipGetLastError());
     if (dvl_status st = mark(3)) return st;
-    hipLaunchKernelGGL((k_bin<MT, S>), dim3(grid), dim3(kUpdThreads), lds, s, a);
+    const size_t lds_bin = ((size_t)a.tf_total * sizeof(float) + 15) / 16 * 16 + (kUpdThreads / kWave) * kRedBytes;
+    hipLaunchKernelGGL((k_bin<MT, S>), dim3(grid), dim3(kUpdThreads), lds_bin, s, a);
     DVL_HIP(hipGetLastError());
     if (dvl_status st = mark(4)) return st;
     const unsigned g4 = (unsigned)((a.W + 3) / 4);

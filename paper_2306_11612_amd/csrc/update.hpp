@@ -13,8 +13,9 @@ constexpr int kTileCells = kStepCells * kTileSteps;  // 4096 cells per wave tile
 
 // Workspace of one update, sized for n_tiles tiles and M fields.
 struct UpdWorkspace {
-    double* tile_sum;     // [T]
-    double* carry;        // [T + 1], carry[T] = F_tot
+    double* local_prefix; // [T]  sum of the importance of earlier tiles of the same run
+    double* run_total;    // [R]  sum over each run of consecutive tiles
+    double* run_base;     // [R + 1]  exclusive prefix of run totals, run_base[R] = F_tot
     int32_t* head_bin;    // [T]
     int32_t* tail_bin;    // [T]
     uint32_t* rec_first;  // [2][T]  head records then tail records
@@ -37,6 +38,8 @@ struct DevParamsHeader {
 struct UpdArgs {
     int64_t n;
     int64_t n_tiles;
+    int64_t tiles_per_run;    // K1 wave r owns tiles [r * tiles_per_run, (r + 1) * tiles_per_run)
+    int64_t n_runs;
     int M;
     int dtype;
     int tf_total;         // sum of the fields' table sizes (LDS floats)
@@ -57,6 +60,11 @@ struct UpdArgs {
     const float* tf;      // concatenated tables, field m at tf_off[m]
     float* vmax_dev;      // parameter block header
     UpdWorkspace ws;
+    // per-tile field statistics of the sorted volume (independent of the TF):
+    // sum [M][T] (fp64), min / max [M][T]
+    const double* agg_sum;
+    const float* agg_min;
+    const float* agg_max;
     // outputs
     uint32_t* first_cell;
     uint32_t* last_cell;
@@ -72,5 +80,9 @@ constexpr int kPhases = 5;   // exact vmax, tile sums, carry, bin, edges
 
 // ev (optional): kPhases + 1 events recorded before the first and after every phase
 dvl_status launch_update(const UpdArgs& a, int n_cu, hipStream_t s, hipEvent_t* ev = nullptr);
+
+// Per-tile sum / min / max of one sorted field (the tiles of the update).
+dvl_status launch_tile_aggregates(int64_t n, int dtype, const void* field, int64_t n_tiles, double* sum,
+                                  float* mn, float* mx, int n_cu, hipStream_t s);
 
 }  // namespace dvl

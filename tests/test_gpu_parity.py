@@ -170,11 +170,59 @@ def test_determinism():
         V.close()
 
 
-def test_cfg2_scaled():
-    """The 3-level AMR workload at base 64 (about 1.5 M cells)."""
+@pytest.fixture(scope="module")
+def cfg2_base64():
     import synth
-    vol = synth.cfg2(device="cuda", base=64).to("cpu")
-    run_case(vol, tfs(synth.SEED + 2, 4, n_cp=(4, 4)), 1920, label="cfg2/base64")
+    return synth.cfg2(device="cuda", base=64).to("cpu")
+
+
+@pytest.mark.parametrize("W,exponent", [(1920, 1.0), (64, 1.0), (7, 2.0), (1, 1.0), (300, 0.0)])
+def test_cfg2_scaled(cfg2_base64, W, exponent):
+    """The 3-level AMR workload at base 64 (about 1.5 M cells).  With few
+    bins most 4096-cell tiles fall inside one bin and take their statistics
+    from the per-tile precomputation instead of a rescan."""
+    import synth
+    run_case(cfg2_base64, tfs(synth.SEED + 2, 4, n_cp=(4, 4)), W, exponent=exponent,
+             label=f"cfg2/base64 W={W}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+def test_sixteen_bit_few_bins(cfg2_base64, dtype):
+    import synth
+    run_case(cfg2_base64, tfs(synth.SEED + 2, 4, n_cp=(4, 4)), 48, dtype=dtype, label=f"{dtype} W=48")
+
+
+def test_set_field_refreshes_tile_statistics(cfg2_base64):
+    """A data change through dvl_set_field: ordering kept, ranges and per-tile
+    statistics refreshed, update equal to a volume built with the new data."""
+    import synth
+    D = dvl()
+    vol = cfg2_base64
+    dev = vol.to("cuda")
+    V = D.build_order(dev.x, dev.y, dev.z, dev.level, dev.fields)
+    try:
+        new = dev.fields[2] * 3.0 + 1.0
+        V.set_field(2, new)
+        fields = list(vol.fields)
+        fields[2] = new.cpu()
+        vol2 = synth.Volume(vol.x, vol.y, vol.z, vol.level, fields)
+        A = tfs(77, 4)
+        _, perm = V.export_order()
+        p = perm.cpu().numpy().view(np.uint32)
+        F = np.stack([f.numpy()[p] for f in fields])
+        lo, hi = oracle.default_windows(F)
+        for m in range(4):
+            assert V.field_range(m) == (float(lo[m]), float(hi[m]))
+            D.set_tf(V, m, A[m], float(lo[m]), float(hi[m]))
+        W = 32
+        bins = D.Bins(W, 4)
+        V.update(bins)
+        g = V.read_bins(bins)
+        ob = oracle.update(vol2.level.numpy()[p], F, A, lo, hi, W, keep_cells=True)
+        from parity import reconcile
+        reconcile(g, ob, F, A, lo, hi, W)
+    finally:
+        V.close()
 
 
 # ---------------------------------------------------------------- errors
