@@ -96,6 +96,24 @@ dvl_status dvl_build_order(int64_t n_cells, const int32_t* x, const int32_t* y,
                            int32_t dtype, const void* const* fields, void* stream,
                            dvl_volume** out);
 
+/* Tuning of a volume's update layout, fixed at build time (results of an
+ * update depend on it only through the summation order of the fp64 prefix).
+ *   tile_steps   cells per tile = 256 * tile_steps; 8, 16 or 32 (0: 16).  The
+ *                projection reads again only tiles that contain a bin edge.
+ *   run_waves    the importance pass splits the tiles into at most this many
+ *                runs of consecutive tiles, one wave each (0: 32 per compute
+ *                unit); 64 <= run_waves <= 65536 otherwise. */
+typedef struct {
+    int32_t tile_steps;
+    int32_t run_waves;
+} dvl_build_options;
+
+/* dvl_build_order with explicit options (NULL: defaults). */
+dvl_status dvl_build_order_ex(int64_t n_cells, const int32_t* x, const int32_t* y,
+                              const int32_t* z, const uint8_t* level, int32_t n_fields,
+                              int32_t dtype, const void* const* fields,
+                              const dvl_build_options* options, void* stream, dvl_volume** out);
+
 /* Replace field m's values (a data change; the order is unchanged).
  * values: device [n_cells] of the volume's dtype, original order.  Re-gathers
  * into sorted order and refreshes the data range; synchronises `stream`.
@@ -169,6 +187,59 @@ typedef struct {
  * DVL_E_STATE, DVL_E_NOMEM (workspace growth), DVL_E_HIP.
  * ------------------------------------------------------------------- */
 dvl_status dvl_update(dvl_volume* v, const dvl_params* p, const dvl_bins* out, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Batched updates (many volumes and TF requests in one launch per phase).
+ *
+ * A request is one update of one volume with its own TFs, windows,
+ * parameters and outputs; it does not touch the volume's own TF state.
+ * Requests on the same volume (up to 8 at a time) share one read of its
+ * cells in the importance pass.  Every request's results are bitwise equal
+ * to those of a dvl_update with the same TFs and parameters, whatever else is
+ * in the batch.  All requests of a batch must share the volumes' storage
+ * dtype.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    dvl_volume* volume;
+    const float* alpha;      /* host [n_fields][n_tf] alpha tables (field-major) */
+    int32_t n_tf;            /* entries per table, 2..4096, n_fields * n_tf <= 16384 */
+    const float* lo;         /* host [n_fields] windows, or NULL for the data ranges */
+    const float* hi;
+    dvl_params params;
+    dvl_bins out;            /* device outputs, caller-owned, [n_fields][params.n_bins] */
+} dvl_request;
+
+/* An executor owns the device descriptors and per-request workspaces of the
+ * batches it runs (grown on demand, reused afterwards).  Use one executor
+ * from one host thread and one stream at a time; batches on different
+ * streams need different executors. */
+typedef struct dvl_executor dvl_executor;
+dvl_status dvl_executor_create(dvl_executor** out);
+void dvl_executor_destroy(dvl_executor* ex);
+/* device bytes held (workspaces and descriptor buffers) */
+size_t dvl_executor_bytes(const dvl_executor* ex);
+/* device workspace a request on this volume with n_bins bins needs */
+size_t dvl_request_bytes(const dvl_volume* v, int32_t n_bins);
+/* per-kernel timing of this executor's batches (see dvl_set_timing) */
+dvl_status dvl_executor_set_timing(dvl_executor* ex, int32_t enable);
+dvl_status dvl_executor_kernel_times(dvl_executor* ex, double* ms, int32_t* n_batches);
+
+/* Enqueue all requests on `stream`: one launch per phase for the whole
+ * batch.  Asynchronous; errors as dvl_update (DVL_E_INVALID also for mixed
+ * dtypes).  Outputs must not overlap between requests. */
+dvl_status dvl_update_batch(dvl_executor* ex, const dvl_request* reqs, int32_t n_reqs, void* stream);
+
+/* A captured batch: the requests (volumes, parameters, outputs, table sizes)
+ * are fixed at creation and the kernels captured once into a HIP graph;
+ * dvl_graph_set_tf changes a request's tables and windows, and
+ * dvl_graph_launch uploads the descriptors and replays the graph.  The graph
+ * owns its workspaces.  Launches of one graph must use one stream. */
+typedef struct dvl_graph dvl_graph;
+dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph** out);
+dvl_status dvl_graph_set_tf(dvl_graph* g, int32_t req, const float* alpha, const float* lo,
+                            const float* hi);
+dvl_status dvl_graph_launch(dvl_graph* g, void* stream);
+void dvl_graph_destroy(dvl_graph* g);
 
 /* Synchronise `stream`, then copy the bins to host arrays (any may be NULL):
  * count/first/last uint32[W], mean/vmin/vmax/y float[M*W], f_total[1],

@@ -1,12 +1,14 @@
 // C ABI of the DVL library: validation, buffer ownership, host-side TF
-// preparation (Eqs. 5-6 run on the host, as in the paper's GPU section) and
-// kernel launches.  Declarations and contracts: include/dvl.h.
+// preparation (Eqs. 5-6 run on the host, as in the paper's GPU section),
+// batch planning and kernel launches.  Declarations and contracts:
+// include/dvl.h.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -43,7 +45,7 @@ static dvl_status fail(dvl_status code, const char* fmt, ...) {
 
 static int elem_bytes_of(int dtype) { return dtype == DVL_F32 ? 4 : 2; }
 
-// device buffer owned by RAII until released into the volume
+// device buffer owned by RAII until released
 struct DevBuf {
     void* p = nullptr;
     ~DevBuf() { if (p) (void)hipFree(p); }
@@ -59,7 +61,20 @@ struct DevBuf {
     void* release() { void* q = p; p = nullptr; return q; }
 };
 
-constexpr int kRing = 4;   // parameter uploads that may be in flight per volume
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// order-preserving uint key (as produced by the range kernel) back to float
+static float unkey(unsigned int u) {
+    const unsigned int b = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+    float f;
+    memcpy(&f, &b, 4);
+    return f;
+}
+
+constexpr int kRing = 4;                 // descriptor uploads that may be in flight
+constexpr int kJobTfFloats = 32768;      // LDS budget of one job's tables (128 KB)
+
+struct Executor;
 
 }  // namespace dvl
 
@@ -67,8 +82,11 @@ using namespace dvl;
 
 struct dvl_volume {
     int64_t n = 0;
-    int64_t n_pad = 0;       // cells rounded up to whole update tiles
+    int64_t n_pad = 0;       // cells rounded up to whole tiles
     int64_t n_tiles = 0;
+    int32_t tile_steps = kDefaultTileSteps;
+    int64_t tiles_per_run = 1;
+    int64_t n_runs = 1;
     int32_t M = 0;
     int32_t dtype = DVL_F32;
     int32_t bits = 0;
@@ -81,87 +99,81 @@ struct dvl_volume {
     uint32_t* perm = nullptr;
     float dmin[kMaxFields] = {};
     float dmax[kMaxFields] = {};
-    // transfer functions (host copies)
-    bool tf_set[kMaxFields] = {};
-    std::vector<float> alpha[kMaxFields];
-    float lo[kMaxFields] = {}, hi[kMaxFields] = {};
-    float qs[kMaxFields] = {}, qb[kMaxFields] = {};
-    // parameter block ring (pinned host staging -> device)
-    size_t param_bytes = 0;
-    void* param_dev[kRing] = {};
-    void* param_host[kRing] = {};
-    hipEvent_t param_ev[kRing] = {};
-    bool param_used[kRing] = {};
-    int param_next = 0;
     // per-tile statistics of the sorted fields: sum [M][T], min [M][T], max [M][T]
     double* agg_sum = nullptr;
     float* agg_min = nullptr;
     float* agg_max = nullptr;
-    // update workspace
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    UpdWorkspace wsv{};
+    // the volume's own transfer functions (used by dvl_update)
+    bool tf_set[kMaxFields] = {};
+    std::vector<float> alpha[kMaxFields];
+    float lo[kMaxFields] = {}, hi[kMaxFields] = {};
+    Executor* ex = nullptr;  // private executor of dvl_update
     dvl_status sticky = DVL_OK;
     size_t bytes = 0;
-    // optional per-kernel timing
-    bool timing = false;
-    std::vector<std::vector<hipEvent_t>> ev_pool, ev_pending;
-    double phase_ms[kPhases] = {};
-    int32_t timed_updates = 0;
 };
 
-namespace {
+namespace dvl {
 
-dvl_status check_sticky(const dvl_volume* v) {
-    if (!v) return fail(DVL_E_INVALID, "volume is NULL");
-    if (v->sticky != DVL_OK) return fail(v->sticky, "volume is in a failed state after an earlier device error");
-    return DVL_OK;
-}
+// ================================================================== host TF prep
 
 // FP32 quantiser of the window [lo, hi] for n_tf entries
-void quantiser(int n_tf, float lo, float hi, float* s, float* b) {
+static void quantiser(int n_tf, float lo, float hi, float* s, float* b) {
     const float sf = (float)((double)n_tf / ((double)hi - (double)lo));
     *s = sf;
     *b = (float)(-(double)lo * (double)sf);
 }
 
-int host_entry(float x, float s, float b, int n_tf) {
+static int host_entry(float x, float s, float b, int n_tf) {
     float t = fmaf(x, s, b);
     if (!(t >= 0.0f)) return 0;
     if (t > (float)(n_tf - 1)) return n_tf - 1;
     return (int)t;
 }
 
+// One update request as the host sees it: tables, windows, parameters, outputs.
+struct ReqHost {
+    dvl_volume* v = nullptr;
+    int n_tf[kMaxFields] = {};       // entries of field m's table
+    int off[kMaxFields] = {};        // start of field m's table in `alpha`
+    int total = 0;                   // floats in `alpha`
+    std::vector<float> alpha;        // tables, field after field
+    float lo[kMaxFields] = {}, hi[kMaxFields] = {};
+    float qs[kMaxFields] = {}, qb[kMaxFields] = {};
+    dvl_params p{};
+    dvl_bins out{};
+    int job = 0;
+    size_t tf_pos = 0;               // floats from the start of the batch's tables
+};
+
 // Eqs. 5-6 and the bound variant (section "Computing the Maximum Local
 // Ensemble Variation"): max(V_h) from the TFs and the fields' data ranges
-float host_vmax(const dvl_volume* v, int mode) {
+static float host_vmax(const ReqHost& r) {
+    const dvl_volume* v = r.v;
     const int M = v->M;
+    auto A = [&](int m, int a) { return r.alpha[(size_t)r.off[m] + std::min(a, r.n_tf[m] - 1)]; };
     int im[kMaxFields], jm[kMaxFields];
     for (int m = 0; m < M; ++m) {
-        const int n_tf = (int)v->alpha[m].size();
-        im[m] = host_entry(v->dmin[m], v->qs[m], v->qb[m], n_tf);
-        jm[m] = host_entry(v->dmax[m], v->qs[m], v->qb[m], n_tf);
+        im[m] = host_entry(v->dmin[m], r.qs[m], r.qb[m], r.n_tf[m]);
+        jm[m] = host_entry(v->dmax[m], r.qs[m], r.qb[m], r.n_tf[m]);
     }
     auto bound = [&]() {
         float hi = -INFINITY, lo = INFINITY;
         for (int m = 0; m < M; ++m)
             for (int a = im[m]; a <= jm[m]; ++a) {
-                hi = std::max(hi, v->alpha[m][a]);
-                lo = std::min(lo, v->alpha[m][a]);
+                hi = std::max(hi, A(m, a));
+                lo = std::min(lo, A(m, a));
             }
         return hi - lo;
     };
-    if (mode == DVL_VMAX_TF_BOUND) return bound();
+    if (r.p.vmax_mode == DVL_VMAX_TF_BOUND) return bound();
     int i = im[0], j = jm[0];
     for (int m = 1; m < M; ++m) { i = std::min(i, im[m]); j = std::max(j, jm[m]); }
     float best = 0.0f;
     for (int a = i; a <= j; ++a) {
         float hi = -INFINITY, lo = INFINITY;
         for (int m = 0; m < M; ++m) {
-            const std::vector<float>& t = v->alpha[m];
-            const float al = t[std::min<int>(a, (int)t.size() - 1)];
-            hi = std::max(hi, al);
-            lo = std::min(lo, al);
+            hi = std::max(hi, A(m, a));
+            lo = std::min(lo, A(m, a));
         }
         best = std::max(best, hi - lo);
     }
@@ -169,9 +181,485 @@ float host_vmax(const dvl_volume* v, int mode) {
     return best;
 }
 
-unsigned grid_small(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
+static dvl_status check_params(const dvl_params* p) {
+    if (!p) return fail(DVL_E_INVALID, "params is NULL");
+    if (p->n_bins < 1 || p->n_bins > (1 << 20)) return fail(DVL_E_INVALID, "n_bins=%d outside [1, 2^20]", p->n_bins);
+    if (!(p->exponent >= 0.0f && p->exponent <= 16.0f)) return fail(DVL_E_INVALID, "exponent %g outside [0, 16]", p->exponent);
+    if (!(p->min_importance >= 0.0f) || !isfinite(p->min_importance))
+        return fail(DVL_E_INVALID, "min_importance %g must be finite and >= 0", p->min_importance);
+    if (p->vmax_mode < 0 || p->vmax_mode > 2) return fail(DVL_E_INVALID, "vmax_mode %d", p->vmax_mode);
+    if (p->clamp_mode < 0 || p->clamp_mode > 1) return fail(DVL_E_INVALID, "clamp_mode %d", p->clamp_mode);
+    if (p->level_scale != 1 && p->level_scale != 3) return fail(DVL_E_INVALID, "level_scale %d (1 or 3)", p->level_scale);
+    if (p->scan_mode < 0 || p->scan_mode > 2) return fail(DVL_E_INVALID, "scan_mode %d", p->scan_mode);
+    return DVL_OK;
+}
 
-}  // namespace
+static dvl_status check_bins(const dvl_bins* b) {
+    if (!b) return fail(DVL_E_INVALID, "bins is NULL");
+    if (!b->first_cell || !b->last_cell || !b->mean || !b->vmin || !b->vmax || !b->y || !b->f_total ||
+        !b->vmax_used)
+        return fail(DVL_E_INVALID, "a bins pointer is NULL");
+    return DVL_OK;
+}
+
+static dvl_status check_volume(const dvl_volume* v) {
+    if (!v) return fail(DVL_E_INVALID, "volume is NULL");
+    if (v->sticky != DVL_OK) return fail(v->sticky, "volume is in a failed state after an earlier device error");
+    return DVL_OK;
+}
+
+// Resolve field m's window (NULL bounds: the data range), its quantiser, and
+// check both are usable in fp32.
+static dvl_status set_window(ReqHost& r, int m, const float* lo, const float* hi) {
+    const dvl_volume* v = r.v;
+    float l = lo ? lo[m] : v->dmin[m], h = hi ? hi[m] : v->dmax[m];
+    if (!lo && !hi && !(h > l)) h = nextafterf(l, INFINITY);   // constant field
+    if (!isfinite(l) || !isfinite(h) || !(l < h))
+        return fail(DVL_E_INVALID, "window [%g, %g] of field %d is not finite with lo < hi", l, h, m);
+    r.lo[m] = l;
+    r.hi[m] = h;
+    quantiser(r.n_tf[m], l, h, &r.qs[m], &r.qb[m]);
+    if (!isfinite(r.qs[m]) || !isfinite(r.qb[m]))
+        return fail(DVL_E_INVALID, "window [%g, %g] of field %d is too narrow for fp32", l, h, m);
+    return DVL_OK;
+}
+
+static dvl_status check_tables(const ReqHost& r) {
+    if (r.total > kMaxTfTotal) return fail(DVL_E_INVALID, "sum of TF sizes %d exceeds %d", r.total, kMaxTfTotal);
+    for (float a : r.alpha)
+        if (!isfinite(a)) return fail(DVL_E_INVALID, "an alpha entry is not finite");
+    return DVL_OK;
+}
+
+// A request from caller inputs: alpha [M][n_tf], windows lo/hi [M] or NULL.
+static dvl_status make_request(dvl_volume* v, const float* alpha, int n_tf, const float* lo, const float* hi,
+                               const dvl_params* p, const dvl_bins* out, ReqHost& r) {
+    if (dvl_status st = check_volume(v)) return st;
+    if (dvl_status st = check_params(p)) return st;
+    if (dvl_status st = check_bins(out)) return st;
+    if (!alpha) return fail(DVL_E_INVALID, "alpha is NULL");
+    if (n_tf < 2 || n_tf > kMaxTfEntries) return fail(DVL_E_INVALID, "n_tf=%d outside [2, %d]", n_tf, kMaxTfEntries);
+    r = ReqHost();
+    r.v = v;
+    for (int m = 0; m < v->M; ++m) {
+        r.n_tf[m] = n_tf;
+        r.off[m] = m * n_tf;
+    }
+    r.total = v->M * n_tf;
+    if (r.total > kMaxTfTotal) return fail(DVL_E_INVALID, "n_fields * n_tf = %d exceeds %d", r.total, kMaxTfTotal);
+    r.alpha.assign(alpha, alpha + r.total);
+    if (dvl_status st = check_tables(r)) return st;
+    for (int m = 0; m < v->M; ++m)
+        if (dvl_status st = set_window(r, m, lo, hi)) return st;
+    r.p = *p;
+    r.out = *out;
+    return DVL_OK;
+}
+
+// A request from the volume's own TF state (dvl_set_tf).
+static dvl_status volume_request(dvl_volume* v, const dvl_params* p, const dvl_bins* out, ReqHost& r) {
+    if (dvl_status st = check_volume(v)) return st;
+    for (int m = 0; m < v->M; ++m)
+        if (!v->tf_set[m]) return fail(DVL_E_STATE, "field %d has no transfer function", m);
+    if (dvl_status st = check_params(p)) return st;
+    if (dvl_status st = check_bins(out)) return st;
+    r = ReqHost();
+    r.v = v;
+    for (int m = 0; m < v->M; ++m) {
+        r.n_tf[m] = (int)v->alpha[m].size();
+        r.off[m] = r.total;
+        r.total += r.n_tf[m];
+        r.alpha.insert(r.alpha.end(), v->alpha[m].begin(), v->alpha[m].end());
+        r.lo[m] = v->lo[m];
+        r.hi[m] = v->hi[m];
+        quantiser(r.n_tf[m], r.lo[m], r.hi[m], &r.qs[m], &r.qb[m]);
+    }
+    r.p = *p;
+    r.out = *out;
+    return DVL_OK;
+}
+
+// the largest importance a cell can reach, times a tile, must stay finite in fp32
+static dvl_status check_range(const ReqHost& r, float vmax) {
+    float amax = -INFINITY, amin = INFINITY;
+    for (float a : r.alpha) { amax = std::max(amax, a); amin = std::min(amin, a); }
+    const double vr = (double)amax - (double)amin;
+    const bool exact = r.p.vmax_mode == DVL_VMAX_EXACT;
+    const double rmax = exact ? 1.0 : (vmax > 0.0f ? vr / (double)vmax : 0.0);
+    const double g = std::max((double)r.p.min_importance, rmax) * ldexp(1.0, r.p.level_scale * r.v->max_level);
+    const double fmax_cell = std::max((double)r.p.min_importance, pow(g, (double)r.p.exponent));
+    if (!(fmax_cell * (double)r.v->tile_steps * kStepCells < 1e37))
+        return fail(DVL_E_RANGE, "importance can reach %g: exponent and levels overflow fp32", fmax_cell);
+    return DVL_OK;
+}
+
+// ================================================================== batch plans
+
+struct Plan {
+    std::vector<ReqHost> reqs;       // grouped by volume
+    std::vector<int> where;          // caller's request index -> index in `reqs`
+    std::vector<JobDev> jobs;
+    std::vector<ReqDev> rdev;
+    int dtype = DVL_F32;
+    int max_m = 1;
+    int max_req = 1;
+    int max_req_tf = 0;
+    int max_job_tf = 0;
+    int any_exact = 0;
+    int64_t k1_units = 0, k3_units = 0, k4_units = 0;
+    size_t tf_floats = 0;
+    // descriptor block: [JobDev x jobs][ReqDev x reqs][max V x reqs][tables]
+    size_t off_jobs = 0, off_reqs = 0, off_vmax = 0, off_tf = 0, block_bytes = 0;
+};
+
+// Group the requests into jobs (one volume; at most kMaxReqPerJob requests
+// whose tables fit the importance pass's LDS) and lay out the work units of
+// every phase and the descriptor block.
+static dvl_status plan_batch(std::vector<ReqHost>&& reqs, Plan& P) {
+    P = Plan();
+    if (reqs.empty()) return fail(DVL_E_INVALID, "empty batch");
+    P.dtype = reqs[0].v->dtype;
+    for (auto& r : reqs)
+        if (r.v->dtype != P.dtype) return fail(DVL_E_INVALID, "a batch mixes field storage types");
+    std::vector<bool> taken(reqs.size(), false);
+    P.where.assign(reqs.size(), 0);
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        if (taken[i]) continue;
+        for (size_t k = i; k < reqs.size(); ++k)
+            if (!taken[k] && reqs[k].v == reqs[i].v) {
+                P.where[k] = (int)P.reqs.size();
+                P.reqs.push_back(std::move(reqs[k]));
+                taken[k] = true;
+            }
+    }
+    size_t tf_pos = 0;
+    for (size_t i = 0; i < P.reqs.size();) {
+        dvl_volume* v = P.reqs[i].v;
+        JobDev j{};
+        j.n = v->n;
+        j.n_tiles = v->n_tiles;
+        j.tiles_per_run = v->tiles_per_run;
+        j.n_runs = v->n_runs;
+        j.k1_unit0 = P.k1_units;
+        j.M = v->M;
+        j.req0 = (int)i;
+        j.tile_steps = v->tile_steps;
+        j.level = v->level_s;
+        for (int m = 0; m < v->M; ++m) j.fields[m] = v->fields_s[m];
+        j.agg_sum = v->agg_sum;
+        j.agg_min = v->agg_min;
+        j.agg_max = v->agg_max;
+        int tf_job = 0;
+        size_t k = i;
+        while (k < P.reqs.size() && P.reqs[k].v == v && (int)(k - i) < kMaxReqPerJob &&
+               (k == i || tf_job + P.reqs[k].total <= kJobTfFloats)) {
+            ReqHost& r = P.reqs[k];
+            r.job = (int)P.jobs.size();
+            r.tf_pos = tf_pos;
+            tf_pos += r.total;
+            tf_job += r.total;
+            P.max_req_tf = std::max(P.max_req_tf, r.total);
+            if (r.p.vmax_mode == DVL_VMAX_EXACT) P.any_exact = 1;
+            ++k;
+        }
+        j.n_req = (int)(k - i);
+        j.tf_total_all = tf_job;
+        P.max_job_tf = std::max(P.max_job_tf, tf_job);
+        P.max_m = std::max(P.max_m, v->M);
+        P.max_req = std::max(P.max_req, j.n_req);
+        // one importance-pass unit is one workgroup: a run per wave
+        P.k1_units += (j.n_runs + (kUpdThreads / kWave) - 1) / (kUpdThreads / kWave);
+        P.jobs.push_back(j);
+        i = k;
+    }
+    // The kernels are specialised on the field count: batches whose volumes
+    // all have M <= 8 fields run the M-field variant; batches that mix field
+    // counts (or have more than 8) run the general one, which reads M per job.
+    for (const JobDev& j : P.jobs)
+        if (j.M != P.jobs[0].M) P.max_m = kMaxFields;
+    if (P.max_m > 8) P.max_m = kMaxFields;
+    P.tf_floats = tf_pos;
+    P.rdev.resize(P.reqs.size());
+    for (size_t q = 0; q < P.reqs.size(); ++q) {
+        const ReqHost& r = P.reqs[q];
+        const JobDev& j = P.jobs[r.job];
+        ReqDev& d = P.rdev[q];
+        d = ReqDev{};
+        for (int m = 0; m < r.v->M; ++m) {
+            d.nmax[m] = (float)(r.n_tf[m] - 1);
+            d.tf_off[m] = r.off[m];
+        }
+        d.tf_job_off = (int)(r.tf_pos - P.reqs[j.req0].tf_pos);
+        d.tf_total = r.total;
+        d.W = r.p.n_bins;
+        d.exponent = r.p.exponent;
+        d.fmin = r.p.min_importance;
+        d.exp_is_one = r.p.exponent == 1.0f;
+        d.clamp_mode = r.p.clamp_mode;
+        d.level_shift = r.p.level_scale;
+        d.scan_mode = r.p.scan_mode;
+        d.vmax_exact = r.p.vmax_mode == DVL_VMAX_EXACT;
+        d.job = r.job;
+        d.k3_unit0 = P.k3_units;
+        d.k4_unit0 = P.k4_units;
+        P.k3_units += j.n_tiles;
+        P.k4_units += r.p.n_bins;
+        d.first_cell = r.out.first_cell;
+        d.last_cell = r.out.last_cell;
+        d.mean = r.out.mean;
+        d.vmin = r.out.vmin;
+        d.vmax = r.out.vmax;
+        d.y = r.out.y;
+        d.f_total = r.out.f_total;
+        d.vmax_used = r.out.vmax_used;
+    }
+    P.off_jobs = 0;
+    P.off_reqs = al256(P.jobs.size() * sizeof(JobDev));
+    P.off_vmax = P.off_reqs + al256(P.rdev.size() * sizeof(ReqDev));
+    P.off_tf = P.off_vmax + al256(P.rdev.size() * sizeof(float));
+    P.block_bytes = P.off_tf + al256(P.tf_floats * sizeof(float));
+    return DVL_OK;
+}
+
+// Write the descriptor block into host image `h` for device address `d`:
+// current tables and quantisers, max(V) of the TF modes (0 for the exact
+// mode, which the first kernel raises with atomics), pointers into the block.
+static dvl_status fill_block(Plan& P, char* h, char* d) {
+    float* vmax_h = (float*)(h + P.off_vmax);
+    float* tf_h = (float*)(h + P.off_tf);
+    for (size_t q = 0; q < P.reqs.size(); ++q) {
+        ReqHost& r = P.reqs[q];
+        const float vm = r.p.vmax_mode == DVL_VMAX_EXACT ? 0.0f : host_vmax(r);
+        if (dvl_status st = check_range(r, vm)) return st;
+        vmax_h[q] = vm;
+        memcpy(tf_h + r.tf_pos, r.alpha.data(), r.alpha.size() * sizeof(float));
+        for (int m = 0; m < r.v->M; ++m) {
+            P.rdev[q].s[m] = r.qs[m];
+            P.rdev[q].b[m] = r.qb[m];
+        }
+        P.rdev[q].tf = (const float*)(d + P.off_tf) + r.tf_pos;
+        P.rdev[q].vmax_dev = (float*)(d + P.off_vmax) + q;
+    }
+    for (auto& j : P.jobs) j.tf_all = (const float*)(d + P.off_tf) + P.reqs[j.req0].tf_pos;
+    memcpy(h + P.off_jobs, P.jobs.data(), P.jobs.size() * sizeof(JobDev));
+    memcpy(h + P.off_reqs, P.rdev.data(), P.rdev.size() * sizeof(ReqDev));
+    return DVL_OK;
+}
+
+static BatchDev batch_dev(const Plan& P, char* d) {
+    BatchDev b{};
+    b.jobs = (const JobDev*)(d + P.off_jobs);
+    b.reqs = (const ReqDev*)(d + P.off_reqs);
+    b.n_jobs = (int)P.jobs.size();
+    b.n_reqs = (int)P.rdev.size();
+    b.k1_units = P.k1_units;
+    b.k3_units = P.k3_units;
+    b.k4_units = P.k4_units;
+    b.any_exact = P.any_exact;
+    b.max_req_tf = P.max_req_tf;
+    b.max_job_tf = P.max_job_tf;
+    return b;
+}
+
+static size_t request_ws_bytes(const dvl_volume* v) { return workspace_bytes(v->n_tiles, v->M); }
+
+// ================================================================== executor
+
+struct Executor {
+    int n_cu = 256;
+    struct Slot {
+        char* host = nullptr;
+        char* dev = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool used = false;
+    };
+    Slot ring[kRing];
+    int next = 0;
+    std::vector<std::pair<void*, size_t>> ws;   // workspace pool: one per request position
+    bool timing = false;
+    std::vector<std::vector<hipEvent_t>> ev_pool, ev_pending;
+    double phase_ms[kPhases] = {};
+    int32_t timed = 0;
+    size_t bytes = 0;
+
+    ~Executor() {
+        (void)hipDeviceSynchronize();
+        for (auto& s : ring) {
+            if (s.host) (void)hipHostFree(s.host);
+            if (s.dev) (void)hipFree(s.dev);
+            if (s.ev) (void)hipEventDestroy(s.ev);
+        }
+        for (auto& w : ws)
+            if (w.first) (void)hipFree(w.first);
+        for (auto* pool : {&ev_pool, &ev_pending})
+            for (auto& set : *pool)
+                for (auto e : set) (void)hipEventDestroy(e);
+    }
+
+    dvl_status init() {
+        int dev = 0;
+        DVL_HIP(hipGetDevice(&dev));
+        DVL_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        for (auto& s : ring) DVL_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+        return DVL_OK;
+    }
+
+    dvl_status ensure_ws(size_t i, size_t need) {
+        if (ws.size() <= i) ws.resize(i + 1, {nullptr, 0});
+        if (ws[i].second >= need) return DVL_OK;
+        if (ws[i].first) {
+            DVL_HIP(hipDeviceSynchronize());   // earlier batches may still use it
+            (void)hipFree(ws[i].first);
+            bytes -= ws[i].second;
+            ws[i] = {nullptr, 0};
+        }
+        DevBuf b;
+        if (dvl_status st = b.alloc(need, "request workspace")) return st;
+        ws[i] = {b.release(), need};
+        bytes += need;
+        return DVL_OK;
+    }
+
+    // the next ring slot, its previous upload complete, large enough for `need`
+    dvl_status take_slot(size_t need, Slot** out) {
+        Slot& s = ring[next];
+        next = (next + 1) % kRing;
+        if (s.used) DVL_HIP(hipEventSynchronize(s.ev));
+        if (s.cap < need) {
+            if (s.dev) {
+                DVL_HIP(hipDeviceSynchronize());   // kernels of earlier batches read it
+                (void)hipFree(s.dev);
+                bytes -= s.cap;
+            }
+            if (s.host) (void)hipHostFree(s.host);
+            s.host = nullptr;
+            s.dev = nullptr;
+            s.cap = 0;
+            const size_t cap = std::max(need * 2, (size_t)65536);
+            if (hipHostMalloc((void**)&s.host, cap, hipHostMallocDefault) != hipSuccess) {
+                s.host = nullptr;
+                (void)hipGetLastError();
+                return fail(DVL_E_NOMEM, "pinned host allocation of %zu bytes failed", cap);
+            }
+            DevBuf d;
+            if (dvl_status st = d.alloc(cap, "batch descriptors")) return st;
+            s.dev = (char*)d.release();
+            s.cap = cap;
+            bytes += cap;
+        }
+        *out = &s;
+        return DVL_OK;
+    }
+
+    dvl_status timing_events(hipEvent_t** out) {
+        *out = nullptr;
+        if (!timing) return DVL_OK;
+        if (ev_pool.empty()) {
+            std::vector<hipEvent_t> set(kPhases + 1, nullptr);
+            for (auto& e : set)
+                if (hipError_t err = hipEventCreate(&e)) {
+                    for (auto x : set)
+                        if (x) (void)hipEventDestroy(x);
+                    return hip_fail(err, "hipEventCreate");
+                }
+            ev_pool.push_back(set);
+        }
+        ev_pending.push_back(ev_pool.back());
+        ev_pool.pop_back();
+        *out = ev_pending.back().data();
+        return DVL_OK;
+    }
+
+    dvl_status run(Plan& P, hipStream_t s) {
+        for (size_t q = 0; q < P.reqs.size(); ++q) {
+            if (dvl_status st = ensure_ws(q, request_ws_bytes(P.reqs[q].v))) return st;
+            workspace_carve(ws[q].first, P.reqs[q].v->n_tiles, P.reqs[q].v->M, &P.rdev[q].ws);
+        }
+        Slot* slot = nullptr;
+        if (dvl_status st = take_slot(P.block_bytes, &slot)) return st;
+        if (dvl_status st = fill_block(P, slot->host, slot->dev)) return st;
+        DVL_HIP(hipMemcpyAsync(slot->dev, slot->host, P.block_bytes, hipMemcpyHostToDevice, s));
+        DVL_HIP(hipEventRecord(slot->ev, s));
+        slot->used = true;
+        hipEvent_t* ev = nullptr;
+        if (dvl_status st = timing_events(&ev)) return st;
+        return launch_batch(batch_dev(P, slot->dev), P.dtype, P.max_m, P.max_req, n_cu, s, ev);
+    }
+
+    dvl_status kernel_times(double* ms, int32_t* n) {
+        for (auto& set : ev_pending) {
+            DVL_HIP(hipEventSynchronize(set[kPhases]));
+            for (int p = 0; p < kPhases; ++p) {
+                float t = 0.0f;
+                DVL_HIP(hipEventElapsedTime(&t, set[p], set[p + 1]));
+                phase_ms[p] += t;
+            }
+            timed += 1;
+            ev_pool.push_back(set);
+        }
+        ev_pending.clear();
+        if (ms)
+            for (int p = 0; p < kPhases; ++p) ms[p] = phase_ms[p];
+        if (n) *n = timed;
+        for (int p = 0; p < kPhases; ++p) phase_ms[p] = 0.0;
+        timed = 0;
+        return DVL_OK;
+    }
+};
+
+static dvl_status new_executor(Executor** out) {
+    Executor* ex = new (std::nothrow) Executor();
+    if (!ex) return fail(DVL_E_NOMEM, "host allocation failed");
+    if (dvl_status st = ex->init()) {
+        delete ex;
+        return st;
+    }
+    *out = ex;
+    return DVL_OK;
+}
+
+static dvl_status requests_from(const dvl_request* reqs, int32_t n, std::vector<ReqHost>& out) {
+    if (!reqs || n < 1) return fail(DVL_E_INVALID, "no requests");
+    out.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const dvl_request& r = reqs[i];
+        if (dvl_status st = make_request(r.volume, r.alpha, r.n_tf, r.lo, r.hi, &r.params, &r.out, out[i])) {
+            const std::string msg = g_err;
+            return fail(st, "request %d: %s", i, msg.c_str());
+        }
+    }
+    return DVL_OK;
+}
+
+}  // namespace dvl
+
+// ================================================================== graphs
+
+struct dvl_graph {
+    Plan plan;
+    int n_cu = 256;
+    char* dev = nullptr;                 // the descriptor block the captured kernels read
+    std::vector<void*> ws;               // one workspace per request
+    char* host[kRing] = {};              // pinned staging of the descriptor block
+    hipEvent_t ev[kRing] = {};
+    bool used[kRing] = {};
+    int next = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~dvl_graph() {
+        (void)hipDeviceSynchronize();
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (dev) (void)hipFree(dev);
+        for (void* w : ws)
+            if (w) (void)hipFree(w);
+        for (int r = 0; r < kRing; ++r) {
+            if (host[r]) (void)hipHostFree(host[r]);
+            if (ev[r]) (void)hipEventDestroy(ev[r]);
+        }
+    }
+};
 
 extern "C" {
 
@@ -180,13 +668,19 @@ const char* dvl_last_error(void) { return g_err.c_str(); }
 size_t dvl_update_workspace_bytes(int64_t n_cells, int32_t n_fields, int32_t n_bins) {
     (void)n_bins;
     if (n_cells < 1 || n_fields < 1) return 0;
-    const int64_t T = (n_cells + kTileCells - 1) / kTileCells;
-    return workspace_bytes(T, n_fields);
+    const int64_t cells = (int64_t)kDefaultTileSteps * kStepCells;
+    return workspace_bytes((n_cells + cells - 1) / cells, n_fields);
 }
 
-dvl_status dvl_build_order(int64_t n, const int32_t* x, const int32_t* y, const int32_t* z,
-                           const uint8_t* level, int32_t M, int32_t dtype, const void* const* fields,
-                           void* stream, dvl_volume** out) {
+size_t dvl_request_bytes(const dvl_volume* v, int32_t n_bins) {
+    if (!v || n_bins < 1) return 0;
+    // workspace + outputs (first/last, mean/min/max/y per field, two scalars)
+    return request_ws_bytes(v) + (size_t)n_bins * (8 + 16 * (size_t)v->M) + 16;
+}
+
+dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, const int32_t* z,
+                              const uint8_t* level, int32_t M, int32_t dtype, const void* const* fields,
+                              const dvl_build_options* opt, void* stream, dvl_volume** out) {
     g_err.clear();
     if (!out) return fail(DVL_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -196,6 +690,15 @@ dvl_status dvl_build_order(int64_t n, const int32_t* x, const int32_t* y, const 
     if (!x || !y || !z || !level || !fields) return fail(DVL_E_INVALID, "NULL input pointer");
     for (int m = 0; m < M; ++m)
         if (!fields[m]) return fail(DVL_E_INVALID, "field %d pointer is NULL", m);
+    int tile_steps = kDefaultTileSteps, run_waves = 0;
+    if (opt) {
+        if (opt->tile_steps != 0 && opt->tile_steps != 8 && opt->tile_steps != 16 && opt->tile_steps != 32)
+            return fail(DVL_E_INVALID, "tile_steps %d (0, 8, 16 or 32)", opt->tile_steps);
+        if (opt->run_waves != 0 && (opt->run_waves < 64 || opt->run_waves > 65536))
+            return fail(DVL_E_INVALID, "run_waves %d outside [64, 65536]", opt->run_waves);
+        if (opt->tile_steps) tile_steps = opt->tile_steps;
+        run_waves = opt->run_waves;
+    }
     hipStream_t s = (hipStream_t)stream;
     const int eb = elem_bytes_of(dtype);
 
@@ -205,10 +708,18 @@ dvl_status dvl_build_order(int64_t n, const int32_t* x, const int32_t* y, const 
     v->n = n;
     v->M = M;
     v->dtype = dtype;
-    v->n_tiles = (n + kTileCells - 1) / kTileCells;
-    v->n_pad = v->n_tiles * kTileCells;
+    v->tile_steps = tile_steps;
+    const int64_t tile_cells = (int64_t)tile_steps * kStepCells;
+    v->n_tiles = (n + tile_cells - 1) / tile_cells;
+    v->n_pad = v->n_tiles * tile_cells;
     DVL_HIP(hipGetDevice(&v->device));
     DVL_HIP(hipDeviceGetAttribute(&v->n_cu, hipDeviceAttributeMultiprocessorCount, v->device));
+    {
+        // runs of consecutive tiles, one per wave of the importance pass
+        const int64_t waves = run_waves ? run_waves : (int64_t)v->n_cu * 32;
+        v->tiles_per_run = std::max<int64_t>(1, (v->n_tiles + waves - 1) / waves);
+        v->n_runs = (v->n_tiles + v->tiles_per_run - 1) / v->tiles_per_run;
+    }
 
     // extent, validity, grid bits
     DevBuf ext;
@@ -260,8 +771,8 @@ dvl_status dvl_build_order(int64_t n, const int32_t* x, const int32_t* y, const 
     v->bytes += (size_t)v->n_pad;
     DevBuf rng;
     if (dvl_status st = rng.alloc((size_t)kMaxFields * 4 * sizeof(unsigned int), "ranges")) return st;
-    std::vector<unsigned int> rinit(kMaxFields * 4);
-    for (int m = 0; m < kMaxFields; ++m) { rinit[m * 4] = 0xFFFFFFFFu; rinit[m * 4 + 1] = 0; rinit[m * 4 + 2] = 0; rinit[m * 4 + 3] = 0; }
+    std::vector<unsigned int> rinit(kMaxFields * 4, 0u);
+    for (int m = 0; m < kMaxFields; ++m) rinit[m * 4] = 0xFFFFFFFFu;
     DVL_HIP(hipMemcpyAsync(rng.p, rinit.data(), rinit.size() * 4, hipMemcpyHostToDevice, s));
     for (int m = 0; m < M; ++m) {
         DevBuf fb;
@@ -283,7 +794,7 @@ dvl_status dvl_build_order(int64_t n, const int32_t* x, const int32_t* y, const 
         v->agg_max = (float*)ax.release();
         v->bytes += mt * 16;
         for (int m = 0; m < M; ++m)
-            if (dvl_status st = launch_tile_aggregates(n, dtype, v->fields_s[m], v->n_tiles,
+            if (dvl_status st = launch_tile_aggregates(n, dtype, v->fields_s[m], v->n_tiles, v->tile_steps,
                                                        v->agg_sum + (size_t)m * v->n_tiles,
                                                        v->agg_min + (size_t)m * v->n_tiles,
                                                        v->agg_max + (size_t)m * v->n_tiles, v->n_cu, s))
@@ -293,44 +804,27 @@ dvl_status dvl_build_order(int64_t n, const int32_t* x, const int32_t* y, const 
     DVL_HIP(hipStreamSynchronize(s));
     for (int m = 0; m < M; ++m) {
         if (rinit[m * 4 + 2]) return fail(DVL_E_RANGE, "field %d holds a NaN", m);
-        auto unkey = [](unsigned int u) {
-            const unsigned int b = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
-            float f;
-            memcpy(&f, &b, 4);
-            return f;
-        };
         v->dmin[m] = unkey(rinit[m * 4]);
         v->dmax[m] = unkey(rinit[m * 4 + 1]);
     }
 
-    // update workspace and parameter ring
-    v->ws_bytes = workspace_bytes(v->n_tiles, M);
-    DevBuf wsb;
-    if (dvl_status st = wsb.alloc(v->ws_bytes, "update workspace")) return st;
-    v->ws = wsb.release();
-    workspace_carve(v->ws, v->n_tiles, M, &v->wsv);
-    v->bytes += v->ws_bytes;
-    v->param_bytes = sizeof(DevParamsHeader) + (size_t)kMaxTfTotal * sizeof(float);
-    for (int r = 0; r < kRing; ++r) {
-        DevBuf pd;
-        if (dvl_status st = pd.alloc(v->param_bytes, "parameter block")) return st;
-        v->param_dev[r] = pd.release();
-        v->bytes += v->param_bytes;
-        if (hipHostMalloc(&v->param_host[r], v->param_bytes, hipHostMallocDefault) != hipSuccess) {
-            v->param_host[r] = nullptr;
-            (void)hipGetLastError();
-            return fail(DVL_E_NOMEM, "pinned host allocation of the parameter block failed");
-        }
-        DVL_HIP(hipEventCreateWithFlags(&v->param_ev[r], hipEventDisableTiming));
-    }
+    // private executor of dvl_update, with the workspace of one request ready
+    if (dvl_status st = new_executor(&v->ex)) return st;
+    if (dvl_status st = v->ex->ensure_ws(0, request_ws_bytes(v))) return st;
     guard.v = nullptr;
     *out = v;
     return DVL_OK;
 }
 
+dvl_status dvl_build_order(int64_t n, const int32_t* x, const int32_t* y, const int32_t* z,
+                           const uint8_t* level, int32_t M, int32_t dtype, const void* const* fields,
+                           void* stream, dvl_volume** out) {
+    return dvl_build_order_ex(n, x, y, z, level, M, dtype, fields, nullptr, stream, out);
+}
+
 dvl_status dvl_set_field(dvl_volume* v, int32_t m, const void* values, void* stream) {
     g_err.clear();
-    if (dvl_status st = check_sticky(v)) return st;
+    if (dvl_status st = check_volume(v)) return st;
     if (m < 0 || m >= v->M) return fail(DVL_E_INVALID, "field index %d outside [0, %d)", m, v->M);
     if (!values) return fail(DVL_E_INVALID, "values is NULL");
     hipStream_t s = (hipStream_t)stream;
@@ -341,7 +835,7 @@ dvl_status dvl_set_field(dvl_volume* v, int32_t m, const void* values, void* str
     DVL_HIP(hipMemcpyAsync(rng.p, r, sizeof r, hipMemcpyHostToDevice, s));
     if (dvl_status st = launch_gather(v->n, v->perm, values, v->fields_s[m], eb, s)) { v->sticky = st; return st; }
     if (dvl_status st = launch_range(v->n, v->dtype, v->fields_s[m], (unsigned int*)rng.p, s)) { v->sticky = st; return st; }
-    if (dvl_status st = launch_tile_aggregates(v->n, v->dtype, v->fields_s[m], v->n_tiles,
+    if (dvl_status st = launch_tile_aggregates(v->n, v->dtype, v->fields_s[m], v->n_tiles, v->tile_steps,
                                                v->agg_sum + (size_t)m * v->n_tiles,
                                                v->agg_min + (size_t)m * v->n_tiles,
                                                v->agg_max + (size_t)m * v->n_tiles, v->n_cu, s)) {
@@ -351,12 +845,6 @@ dvl_status dvl_set_field(dvl_volume* v, int32_t m, const void* values, void* str
     DVL_HIP(hipMemcpyAsync(r, rng.p, sizeof r, hipMemcpyDeviceToHost, s));
     DVL_HIP(hipStreamSynchronize(s));
     if (r[2]) return fail(DVL_E_RANGE, "field %d holds a NaN", m);
-    auto unkey = [](unsigned int u) {
-        const unsigned int b = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
-        float f;
-        memcpy(&f, &b, 4);
-        return f;
-    };
     v->dmin[m] = unkey(r[0]);
     v->dmax[m] = unkey(r[1]);
     return DVL_OK;
@@ -373,7 +861,7 @@ dvl_status dvl_field_range(const dvl_volume* v, int32_t m, float* vmin, float* v
 
 dvl_status dvl_set_tf(dvl_volume* v, int32_t m, const float* alpha, int32_t n_tf, float lo, float hi) {
     g_err.clear();
-    if (dvl_status st = check_sticky(v)) return st;
+    if (dvl_status st = check_volume(v)) return st;
     if (m < 0 || m >= v->M) return fail(DVL_E_INVALID, "field index %d outside [0, %d)", m, v->M);
     if (!alpha) return fail(DVL_E_INVALID, "alpha is NULL");
     if (n_tf < 2 || n_tf > kMaxTfEntries) return fail(DVL_E_INVALID, "n_tf=%d outside [2, %d]", n_tf, kMaxTfEntries);
@@ -390,115 +878,18 @@ dvl_status dvl_set_tf(dvl_volume* v, int32_t m, const float* alpha, int32_t n_tf
     v->alpha[m].assign(alpha, alpha + n_tf);
     v->lo[m] = lo;
     v->hi[m] = hi;
-    v->qs[m] = s;
-    v->qb[m] = b;
     v->tf_set[m] = true;
     return DVL_OK;
 }
 
 dvl_status dvl_update(dvl_volume* v, const dvl_params* p, const dvl_bins* out, void* stream) {
     g_err.clear();
-    if (dvl_status st = check_sticky(v)) return st;
-    if (!p || !out) return fail(DVL_E_INVALID, "params or bins is NULL");
-    if (p->n_bins < 1 || p->n_bins > (1 << 20)) return fail(DVL_E_INVALID, "n_bins=%d outside [1, 2^20]", p->n_bins);
-    if (!(p->exponent >= 0.0f && p->exponent <= 16.0f)) return fail(DVL_E_INVALID, "exponent %g outside [0, 16]", p->exponent);
-    if (!(p->min_importance >= 0.0f) || !isfinite(p->min_importance)) return fail(DVL_E_INVALID, "min_importance %g must be finite and >= 0", p->min_importance);
-    if (p->vmax_mode < 0 || p->vmax_mode > 2) return fail(DVL_E_INVALID, "vmax_mode %d", p->vmax_mode);
-    if (p->clamp_mode < 0 || p->clamp_mode > 1) return fail(DVL_E_INVALID, "clamp_mode %d", p->clamp_mode);
-    if (p->level_scale != 1 && p->level_scale != 3) return fail(DVL_E_INVALID, "level_scale %d (1 or 3)", p->level_scale);
-    if (p->scan_mode < 0 || p->scan_mode > 2) return fail(DVL_E_INVALID, "scan_mode %d", p->scan_mode);
-    if (!out->first_cell || !out->last_cell || !out->mean || !out->vmin || !out->vmax || !out->y ||
-        !out->f_total || !out->vmax_used)
-        return fail(DVL_E_INVALID, "a bins pointer is NULL");
-    for (int m = 0; m < v->M; ++m)
-        if (!v->tf_set[m]) return fail(DVL_E_STATE, "field %d has no transfer function", m);
-    hipStream_t s = (hipStream_t)stream;
-
-    UpdArgs a{};
-    a.n = v->n;
-    a.n_tiles = v->n_tiles;
-    {
-        // runs of consecutive tiles, one per wave of the importance pass
-        const int64_t waves = (int64_t)v->n_cu * 8 * (kUpdThreads / kWave);
-        a.tiles_per_run = std::max<int64_t>(1, (v->n_tiles + waves - 1) / waves);
-        a.n_runs = (v->n_tiles + a.tiles_per_run - 1) / a.tiles_per_run;
-    }
-    a.M = v->M;
-    a.dtype = v->dtype;
-    a.W = p->n_bins;
-    a.exponent = p->exponent;
-    a.fmin = p->min_importance;
-    a.exp_is_one = p->exponent == 1.0f;
-    a.clamp_mode = p->clamp_mode;
-    a.level_shift = p->level_scale;
-    a.scan_mode = p->scan_mode;
-    a.vmax_exact = p->vmax_mode == DVL_VMAX_EXACT;
-    int off = 0;
-    float amax = -INFINITY, amin = INFINITY;
-    for (int m = 0; m < v->M; ++m) {
-        a.s[m] = v->qs[m];
-        a.b[m] = v->qb[m];
-        a.nmax[m] = (float)(v->alpha[m].size() - 1);
-        a.tf_off[m] = off;
-        off += (int)v->alpha[m].size();
-        for (float al : v->alpha[m]) { amax = std::max(amax, al); amin = std::min(amin, al); }
-    }
-    a.tf_total = off;
-    const float vmax = a.vmax_exact ? 0.0f : host_vmax(v, p->vmax_mode);
-
-    // overflow guard: the largest possible importance times a tile must stay finite in fp32
-    {
-        const double vr = (double)amax - (double)amin;
-        const double rmax = a.vmax_exact ? 1.0 : (vmax > 0.0f ? vr / (double)vmax : 0.0);
-        const double g = std::max((double)p->min_importance, rmax) * ldexp(1.0, p->level_scale * v->max_level);
-        const double fmax_cell = std::max((double)p->min_importance, pow(g, (double)p->exponent));
-        if (!(fmax_cell * kTileCells < 1e37)) return fail(DVL_E_RANGE, "importance can reach %g: exponent and levels overflow fp32", fmax_cell);
-    }
-
-    // stage the parameter block: header (max V) + concatenated TF tables
-    const int r = v->param_next;
-    v->param_next = (r + 1) % kRing;
-    if (v->param_used[r]) DVL_HIP(hipEventSynchronize(v->param_ev[r]));
-    char* hp = (char*)v->param_host[r];
-    DevParamsHeader hdr{};
-    hdr.vmax = vmax;
-    memcpy(hp, &hdr, sizeof hdr);
-    float* tfh = (float*)(hp + sizeof(DevParamsHeader));
-    for (int m = 0; m < v->M; ++m) memcpy(tfh + a.tf_off[m], v->alpha[m].data(), v->alpha[m].size() * 4);
-    const size_t bytes = sizeof(DevParamsHeader) + (size_t)off * 4;
-    DVL_HIP(hipMemcpyAsync(v->param_dev[r], hp, bytes, hipMemcpyHostToDevice, s));
-    DVL_HIP(hipEventRecord(v->param_ev[r], s));
-    v->param_used[r] = true;
-
-    a.vmax_dev = (float*)v->param_dev[r];
-    a.tf = (const float*)((char*)v->param_dev[r] + sizeof(DevParamsHeader));
-    a.level = v->level_s;
-    for (int m = 0; m < v->M; ++m) a.fields[m] = v->fields_s[m];
-    a.ws = v->wsv;
-    a.agg_sum = v->agg_sum;
-    a.agg_min = v->agg_min;
-    a.agg_max = v->agg_max;
-    a.first_cell = out->first_cell;
-    a.last_cell = out->last_cell;
-    a.mean = out->mean;
-    a.vmin = out->vmin;
-    a.vmax = out->vmax;
-    a.y = out->y;
-    a.f_total = out->f_total;
-    a.vmax_used = out->vmax_used;
-    hipEvent_t* ev = nullptr;
-    if (v->timing) {
-        if (v->ev_pool.empty()) {
-            std::vector<hipEvent_t> set(kPhases + 1);
-            for (auto& e : set) DVL_HIP(hipEventCreate(&e));
-            v->ev_pool.push_back(set);
-        }
-        v->ev_pending.push_back(v->ev_pool.back());
-        v->ev_pool.pop_back();
-        ev = v->ev_pending.back().data();
-    }
-    dvl_status st = launch_update(a, v->n_cu, s, ev);
-    if (st != DVL_OK) v->sticky = st;
+    std::vector<ReqHost> reqs(1);
+    if (dvl_status st = volume_request(v, p, out, reqs[0])) return st;
+    Plan P;
+    if (dvl_status st = plan_batch(std::move(reqs), P)) return st;
+    const dvl_status st = v->ex->run(P, (hipStream_t)stream);
+    if (st == DVL_E_HIP) v->sticky = st;
     return st;
 }
 
@@ -506,7 +897,7 @@ dvl_status dvl_read_bins(const dvl_volume* v, const dvl_bins* b, int32_t W, void
                          uint32_t* first, uint32_t* last, float* mean, float* vmin, float* vmax, float* y,
                          double* f_total, float* vmax_used) {
     g_err.clear();
-    if (dvl_status st = check_sticky(v)) return st;
+    if (dvl_status st = check_volume(v)) return st;
     if (!b) return fail(DVL_E_INVALID, "bins is NULL");
     if (W < 1 || W > (1 << 20)) return fail(DVL_E_INVALID, "n_bins=%d outside [1, 2^20]", W);
     hipStream_t s = (hipStream_t)stream;
@@ -532,7 +923,7 @@ dvl_status dvl_read_bins(const dvl_volume* v, const dvl_bins* b, int32_t W, void
 
 dvl_status dvl_export_order(const dvl_volume* v, uint64_t* keys, uint32_t* perm, void* stream) {
     g_err.clear();
-    if (dvl_status st = check_sticky(v)) return st;
+    if (dvl_status st = check_volume(v)) return st;
     hipStream_t s = (hipStream_t)stream;
     if (keys) {
         if (dvl_status st = launch_scatter_back(v->n, v->perm, v->keys_s, keys, 8, s)) return st;
@@ -543,7 +934,7 @@ dvl_status dvl_export_order(const dvl_volume* v, uint64_t* keys, uint32_t* perm,
 
 dvl_status dvl_export_sorted(const dvl_volume* v, uint8_t* level, void* const* fields, void* stream) {
     g_err.clear();
-    if (dvl_status st = check_sticky(v)) return st;
+    if (dvl_status st = check_volume(v)) return st;
     hipStream_t s = (hipStream_t)stream;
     if (level) DVL_HIP(hipMemcpyAsync(level, v->level_s, (size_t)v->n, hipMemcpyDeviceToDevice, s));
     if (fields) {
@@ -556,60 +947,167 @@ dvl_status dvl_export_sorted(const dvl_volume* v, uint8_t* level, void* const* f
 
 dvl_status dvl_set_timing(dvl_volume* v, int32_t enable) {
     g_err.clear();
-    if (dvl_status st = check_sticky(v)) return st;
-    v->timing = enable != 0;
+    if (dvl_status st = check_volume(v)) return st;
+    v->ex->timing = enable != 0;
     return DVL_OK;
 }
 
 dvl_status dvl_kernel_times(dvl_volume* v, double* ms, int32_t* n_updates) {
     g_err.clear();
-    if (dvl_status st = check_sticky(v)) return st;
-    for (auto& set : v->ev_pending) {
-        DVL_HIP(hipEventSynchronize(set[kPhases]));
-        for (int p = 0; p < kPhases; ++p) {
-            float t = 0.0f;
-            DVL_HIP(hipEventElapsedTime(&t, set[p], set[p + 1]));
-            v->phase_ms[p] += t;
-        }
-        v->timed_updates += 1;
-        v->ev_pool.push_back(set);
-    }
-    v->ev_pending.clear();
-    if (ms)
-        for (int p = 0; p < kPhases; ++p) ms[p] = v->phase_ms[p];
-    if (n_updates) *n_updates = v->timed_updates;
-    for (int p = 0; p < kPhases; ++p) v->phase_ms[p] = 0.0;
-    v->timed_updates = 0;
-    return DVL_OK;
+    if (dvl_status st = check_volume(v)) return st;
+    return v->ex->kernel_times(ms, n_updates);
 }
 
 int64_t dvl_num_cells(const dvl_volume* v) { return v ? v->n : 0; }
 int32_t dvl_num_fields(const dvl_volume* v) { return v ? v->M : 0; }
 int32_t dvl_grid_bits(const dvl_volume* v) { return v ? v->bits : 0; }
 int32_t dvl_dtype(const dvl_volume* v) { return v ? v->dtype : -1; }
-size_t dvl_volume_bytes(const dvl_volume* v) { return v ? v->bytes : 0; }
+size_t dvl_volume_bytes(const dvl_volume* v) { return v ? v->bytes + (v->ex ? v->ex->bytes : 0) : 0; }
 
 void dvl_destroy(dvl_volume* v) {
     if (!v) return;
     (void)hipDeviceSynchronize();
+    delete v->ex;
     if (v->level_s) (void)hipFree(v->level_s);
     for (int m = 0; m < kMaxFields; ++m)
         if (v->fields_s[m]) (void)hipFree(v->fields_s[m]);
     if (v->keys_s) (void)hipFree(v->keys_s);
     if (v->perm) (void)hipFree(v->perm);
-    if (v->ws) (void)hipFree(v->ws);
     if (v->agg_sum) (void)hipFree(v->agg_sum);
     if (v->agg_min) (void)hipFree(v->agg_min);
     if (v->agg_max) (void)hipFree(v->agg_max);
-    for (auto* pool : {&v->ev_pool, &v->ev_pending})
-        for (auto& set : *pool)
-            for (auto e : set) (void)hipEventDestroy(e);
-    for (int r = 0; r < kRing; ++r) {
-        if (v->param_dev[r]) (void)hipFree(v->param_dev[r]);
-        if (v->param_host[r]) (void)hipHostFree(v->param_host[r]);
-        if (v->param_ev[r]) (void)hipEventDestroy(v->param_ev[r]);
-    }
     delete v;
 }
+
+// ------------------------------------------------------------------ executors and batches
+
+dvl_status dvl_executor_create(dvl_executor** out) {
+    g_err.clear();
+    if (!out) return fail(DVL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    Executor* ex = nullptr;
+    if (dvl_status st = new_executor(&ex)) return st;
+    *out = reinterpret_cast<dvl_executor*>(ex);
+    return DVL_OK;
+}
+
+void dvl_executor_destroy(dvl_executor* ex) { delete reinterpret_cast<Executor*>(ex); }
+
+size_t dvl_executor_bytes(const dvl_executor* ex) {
+    return ex ? reinterpret_cast<const Executor*>(ex)->bytes : 0;
+}
+
+dvl_status dvl_executor_set_timing(dvl_executor* ex, int32_t enable) {
+    g_err.clear();
+    if (!ex) return fail(DVL_E_INVALID, "executor is NULL");
+    reinterpret_cast<Executor*>(ex)->timing = enable != 0;
+    return DVL_OK;
+}
+
+dvl_status dvl_executor_kernel_times(dvl_executor* ex, double* ms, int32_t* n) {
+    g_err.clear();
+    if (!ex) return fail(DVL_E_INVALID, "executor is NULL");
+    return reinterpret_cast<Executor*>(ex)->kernel_times(ms, n);
+}
+
+dvl_status dvl_update_batch(dvl_executor* exh, const dvl_request* reqs, int32_t n_reqs, void* stream) {
+    g_err.clear();
+    if (!exh) return fail(DVL_E_INVALID, "executor is NULL");
+    std::vector<ReqHost> rh;
+    if (dvl_status st = requests_from(reqs, n_reqs, rh)) return st;
+    Plan P;
+    if (dvl_status st = plan_batch(std::move(rh), P)) return st;
+    return reinterpret_cast<Executor*>(exh)->run(P, (hipStream_t)stream);
+}
+
+dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph** out) {
+    g_err.clear();
+    if (!out) return fail(DVL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    std::vector<ReqHost> rh;
+    if (dvl_status st = requests_from(reqs, n_reqs, rh)) return st;
+    dvl_graph* g = new (std::nothrow) dvl_graph();
+    if (!g) return fail(DVL_E_NOMEM, "host allocation failed");
+    struct Guard { dvl_graph* g; ~Guard() { delete g; } } guard{g};
+    if (dvl_status st = plan_batch(std::move(rh), g->plan)) return st;
+    Plan& P = g->plan;
+    int dev = 0;
+    DVL_HIP(hipGetDevice(&dev));
+    DVL_HIP(hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    for (size_t q = 0; q < P.reqs.size(); ++q) {
+        DevBuf w;
+        if (dvl_status st = w.alloc(request_ws_bytes(P.reqs[q].v), "request workspace")) return st;
+        g->ws.push_back(w.release());
+        workspace_carve(g->ws.back(), P.reqs[q].v->n_tiles, P.reqs[q].v->M, &P.rdev[q].ws);
+    }
+    DevBuf d;
+    if (dvl_status st = d.alloc(P.block_bytes, "graph descriptors")) return st;
+    g->dev = (char*)d.release();
+    {
+        // a first descriptor image validates the tables (range checks) before anything is captured
+        std::vector<char> probe(P.block_bytes);
+        if (dvl_status st = fill_block(P, probe.data(), g->dev)) return st;
+    }
+    for (int r = 0; r < kRing; ++r) {
+        if (hipHostMalloc((void**)&g->host[r], P.block_bytes, hipHostMallocDefault) != hipSuccess) {
+            g->host[r] = nullptr;
+            (void)hipGetLastError();
+            return fail(DVL_E_NOMEM, "pinned host allocation failed");
+        }
+        DVL_HIP(hipEventCreateWithFlags(&g->ev[r], hipEventDisableTiming));
+    }
+    // capture the kernels once; the descriptors they read are refreshed before each replay
+    hipStream_t cs;
+    DVL_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    if (hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    const dvl_status cst = launch_batch(batch_dev(P, g->dev), P.dtype, P.max_m, P.max_req, g->n_cu, cs, nullptr);
+    const hipError_t ee = hipStreamEndCapture(cs, &g->graph);
+    (void)hipStreamDestroy(cs);
+    if (cst != DVL_OK) return cst;
+    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+    DVL_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    guard.g = nullptr;
+    *out = g;
+    return DVL_OK;
+}
+
+dvl_status dvl_graph_set_tf(dvl_graph* g, int32_t req, const float* alpha, const float* lo, const float* hi) {
+    g_err.clear();
+    if (!g) return fail(DVL_E_INVALID, "graph is NULL");
+    Plan& P = g->plan;
+    if (req < 0 || req >= (int)P.where.size())
+        return fail(DVL_E_INVALID, "request %d outside [0, %zu)", req, P.where.size());
+    ReqHost& r = P.reqs[P.where[req]];
+    ReqHost tmp;
+    if (dvl_status st = make_request(r.v, alpha, r.n_tf[0], lo, hi, &r.p, &r.out, tmp)) return st;
+    r.alpha = std::move(tmp.alpha);
+    for (int m = 0; m < r.v->M; ++m) {
+        r.lo[m] = tmp.lo[m];
+        r.hi[m] = tmp.hi[m];
+        r.qs[m] = tmp.qs[m];
+        r.qb[m] = tmp.qb[m];
+    }
+    return DVL_OK;
+}
+
+dvl_status dvl_graph_launch(dvl_graph* g, void* stream) {
+    g_err.clear();
+    if (!g) return fail(DVL_E_INVALID, "graph is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int r = g->next;
+    if (g->used[r]) DVL_HIP(hipEventSynchronize(g->ev[r]));
+    if (dvl_status st = fill_block(g->plan, g->host[r], g->dev)) return st;
+    g->next = (r + 1) % kRing;
+    DVL_HIP(hipMemcpyAsync(g->dev, g->host[r], g->plan.block_bytes, hipMemcpyHostToDevice, s));
+    DVL_HIP(hipEventRecord(g->ev[r], s));
+    g->used[r] = true;
+    DVL_HIP(hipGraphLaunch(g->exec, s));
+    return DVL_OK;
+}
+
+void dvl_graph_destroy(dvl_graph* g) { delete g; }
 
 }  // extern "C"

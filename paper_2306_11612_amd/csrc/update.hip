@@ -1,30 +1,33 @@
 // Per-update kernels of dynamic volume lines (Eqs. 1-4 and section
-// "Projecting Cells to 1D" of Zellmann et al., arXiv 2306.11612).
+// "Projecting Cells to 1D" of Zellmann et al., arXiv 2306.11612), over a
+// batch of jobs (a job = one volume and up to 8 TF requests).
 //
-//   K0 k_vmax_exact   (DVL_VMAX_EXACT only) max over cells of V_h
-//   K1 k_tile_sums    TF lookup, V_h (Eq. 1), importance f (Eq. 3) and the
-//                     fp64 sum of f over every 4096-cell tile; each wave owns
-//                     a run of consecutive tiles and records their prefix
-//                     inside the run
-//   K2 k_carry        exclusive scan of the run totals (Eq. 4 across runs,
-//                     fp64 or compensated fp32), made monotone
-//   K3 k_bin          per tile: if its pixel interval lies inside one bin,
-//                     the tile's precomputed field statistics are its record;
-//                     otherwise recompute f, in-tile monotone prefix, pixel
-//                     interval of every cell; bins complete inside the tile
-//                     are finalised directly, its first and last bin go to
-//                     per-tile partial records
-//   K4 k_edges        merge the partial records of bins shared by tiles in
-//                     tile order; mean, min, max and height y = alpha(mean)
+//   K0 k_vmax_exact   (DVL_VMAX_EXACT requests only) max over cells of V_h
+//   K1 k_tile_sums    TF lookup, V_h (Eq. 1) and importance f (Eq. 3) of every
+//                     cell for every request of its job (one read of the
+//                     cells); fp64 sum of f per tile; each wave owns a run of
+//                     consecutive tiles and records their prefix inside it
+//   K2 k_carry        per request: exclusive scan of the run totals (Eq. 4
+//                     across runs; fp64 or compensated fp32), made monotone
+//   K3 k_bin          per (request, tile): if the tile's pixel interval lies
+//                     inside one bin, its precomputed field statistics are its
+//                     record; otherwise recompute f, monotone in-tile prefix,
+//                     pixel interval of every cell; bins complete inside the
+//                     tile are finalised directly, its first and last bin go
+//                     to per-tile partial records
+//   K4 k_edges        per (request, bin): merge the partial records of bins
+//                     shared by tiles in tile order; mean, min, max, height
 //
 // The paper's GPU version runs the projection once per field with global
 // atomics on the W bins (its Table 1 bottleneck).  Here the projection is
-// hierarchical over 4096-cell tiles (the paper's future-work suggestion):
-// only tiles that contain a bin edge are read again, all fields at once and
-// atomic-free (per-lane accumulators while a 256-cell step stays in one bin,
-// a per-bin wave reduction at bin edges).  Results are bitwise deterministic.
+// hierarchical over tiles (the paper's future-work suggestion): only tiles
+// that contain a bin edge are read again, all fields at once and atomic-free
+// (per-lane accumulators while a 256-cell step stays in one bin, a per-bin
+// wave reduction at bin edges).  Results are bitwise deterministic and do not
+// depend on what else is in the batch.
 #include "update.hpp"
 
+#include <algorithm>
 #include <climits>
 
 namespace dvl {
@@ -62,6 +65,34 @@ void workspace_carve(void* base, int64_t T, int M, UpdWorkspace* w) {
     w->scal = (double*)take(8 * 8);
 }
 
+// ------------------------------------------------------------------ unit lookup
+
+// last job whose first importance-pass unit is <= u
+__device__ __forceinline__ int find_job_k1(const BatchDev& b, int64_t u) {
+    int lo = 0, hi = b.n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.jobs[mid].k1_unit0 <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int find_req_k3(const BatchDev& b, int64_t u) {
+    int lo = 0, hi = b.n_reqs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.reqs[mid].k3_unit0 <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int find_req_k4(const BatchDev& b, int64_t u) {
+    int lo = 0, hi = b.n_reqs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.reqs[mid].k4_unit0 <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ------------------------------------------------------------------ per-cell math
 
 struct ImpCtx {
@@ -73,15 +104,15 @@ struct ImpCtx {
     int lshift;
 };
 
-__device__ __forceinline__ ImpCtx make_ctx(const UpdArgs& a) {
+__device__ __forceinline__ ImpCtx make_ctx(const ReqDev& q) {
     ImpCtx c;
-    const float vm = *a.vmax_dev;
+    const float vm = *q.vmax_dev;
     c.inv_vmax = vm > 0.0f ? 1.0f / vm : 0.0f;
-    c.fmin = a.fmin;
-    c.p = a.exponent;
-    c.exp_is_one = a.exp_is_one;
-    c.clamp_mode = a.clamp_mode;
-    c.lshift = a.level_shift;
+    c.fmin = q.fmin;
+    c.p = q.exponent;
+    c.exp_is_one = q.exp_is_one;
+    c.clamp_mode = q.clamp_mode;
+    c.lshift = q.level_shift;
     return c;
 }
 
@@ -92,16 +123,16 @@ __device__ __forceinline__ int tf_entry(float x, float s, float b, float nmax) {
     return (int)t;
 }
 
-// Eq. 1: V = max_m alpha_m(x_m) - min_m alpha_m(x_m)
+// Eq. 1: V = max_m alpha_m(x_m) - min_m alpha_m(x_m); `tf` is the request's block
 template <int MT>
 __device__ __forceinline__ float variation(const float (&x)[MT], int M, const float* __restrict__ tf,
-                                           const UpdArgs& a, const ImpCtx& c) {
+                                           const ReqDev& q) {
     float amax = -INFINITY, amin = INFINITY;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         if (m < M) {
-            const int e = tf_entry(x[m], a.s[m], a.b[m], a.nmax[m]);
-            const float al = tf[a.tf_off[m] + e];
+            const int e = tf_entry(x[m], q.s[m], q.b[m], q.nmax[m]);
+            const float al = tf[q.tf_off[m] + e];
             amax = fmaxf(amax, al);
             amin = fminf(amin, al);
         }
@@ -125,14 +156,11 @@ __device__ __forceinline__ float importance_from_v(float v, uint32_t L, const Im
     return f;
 }
 
-__device__ __forceinline__ void load_tf(float* lds, const float* tf, int count) {
-    for (int i = threadIdx.x; i < count; i += blockDim.x) lds[i] = tf[i];
-    __syncthreads();
-}
-
+// Field count of a job: the variants MT <= 8 run batches whose jobs all have
+// exactly MT fields (a compile-time count); MT = 16 reads it per job.
 template <int MT>
-__device__ __forceinline__ int fields_of(const UpdArgs& a) {
-    return MT <= 8 ? MT : a.M;
+__device__ __forceinline__ int fields_of(int M) {
+    return MT <= 8 ? MT : M;
 }
 
 // values of the 4 cells of this lane in the given step
@@ -140,44 +168,69 @@ template <int MT, typename S>
 struct StepData {
     Quad<S> q[MT];
     uint32_t lv;
-    __device__ __forceinline__ void load(const UpdArgs& a, int M, int64_t quad) {
+    __device__ __forceinline__ void load(const JobDev& j, int M, int64_t quad) {
 #pragma unroll
         for (int m = 0; m < MT; ++m)
-            if (m < M) q[m].load(a.fields[m], quad);
-        lv = reinterpret_cast<const uint32_t*>(a.level)[quad];
+            if (m < M) q[m].load(j.fields[m], quad);
+        lv = reinterpret_cast<const uint32_t*>(j.level)[quad];
     }
 };
 
 // ------------------------------------------------------------------ K0
 
-template <int MT, typename S>
-__global__ __launch_bounds__(kUpdThreads) void k_vmax_exact(UpdArgs a) {
+template <int MT, typename S, int KR>
+__global__ __launch_bounds__(kUpdThreads) void k_vmax_exact(BatchDev b) {
     extern __shared__ float tf_lds[];
-    load_tf(tf_lds, a.tf, a.tf_total);
-    const int M = fields_of<MT>(a);
-    const ImpCtx c = make_ctx(a);
     const int lane = lane_id();
-    const int64_t wave = (int64_t)blockIdx.x * (kUpdThreads / kWave) + threadIdx.x / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * (kUpdThreads / kWave);
-    float vmax = 0.0f;
-    for (int64_t t = wave; t < a.n_tiles; t += nwaves) {
-        for (int s = 0; s < kTileSteps; ++s) {
-            const int64_t c0 = t * kTileCells + (int64_t)s * kStepCells;
-            if (c0 >= a.n) break;
-            const int64_t quad = (c0 >> 2) + lane;
+    const int wv = threadIdx.x / kWave;
+    int loaded = -1;
+    for (int64_t u = blockIdx.x; u < b.k1_units; u += gridDim.x) {
+        const int ji = find_job_k1(b, u);
+        const JobDev& j = b.jobs[ji];
+        if (ji != loaded) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < j.tf_total_all; i += blockDim.x) tf_lds[i] = j.tf_all[i];
+            __syncthreads();
+            loaded = ji;
+        }
+        const int M = fields_of<MT>(j.M);
+        const int64_t r = (u - j.k1_unit0) * (kUpdThreads / kWave) + wv;
+        if (r >= j.n_runs) continue;
+        const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
+        const int64_t c_begin = r * j.tiles_per_run * tile_cells;
+        const int64_t c_end = min(j.n, (r + 1) * j.tiles_per_run * tile_cells);
+        const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
+        float vmax[KR];
+#pragma unroll
+        for (int q = 0; q < KR; ++q) vmax[q] = 0.0f;
+        for (int s = 0; s < nsteps; ++s) {
+            const int64_t quad = ((c_begin + (int64_t)s * kStepCells) >> 2) + lane;
             StepData<MT, S> d;
-            d.load(a, M, quad);
+            d.load(j, M, quad);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 float x[MT];
 #pragma unroll
                 for (int m = 0; m < MT; ++m) x[m] = m < M ? d.q[m].get(k) : 0.0f;
-                if ((quad << 2) + k < a.n) vmax = fmaxf(vmax, variation<MT>(x, M, tf_lds, a, c));
+                if ((quad << 2) + k >= j.n) continue;
+#pragma unroll
+                for (int q = 0; q < KR; ++q) {
+                    if (q < j.n_req && b.reqs[j.req0 + q].vmax_exact) {
+                        const ReqDev& rq = b.reqs[j.req0 + q];
+                        vmax[q] = fmaxf(vmax[q], variation<MT>(x, M, tf_lds + rq.tf_job_off, rq));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KR; ++q) {
+            if (q < j.n_req && b.reqs[j.req0 + q].vmax_exact) {
+                const float v = wave_max_f(vmax[q]);
+                if (lane == 0 && v > 0.0f)
+                    atomicMax(reinterpret_cast<unsigned int*>(b.reqs[j.req0 + q].vmax_dev), __float_as_uint(v));
             }
         }
     }
-    vmax = wave_max_f(vmax);
-    if (lane == 0 && vmax > 0.0f) atomicMax(reinterpret_cast<unsigned int*>(a.vmax_dev), __float_as_uint(vmax));
 }
 
 // ------------------------------------------------------------------ K1
@@ -206,59 +259,97 @@ struct RunAcc {
     }
 };
 
-// Wave r owns the run of consecutive tiles [r k, (r + 1) k): it streams their
-// cells, sums the importance f of every 4096-cell tile in fp64 and records,
-// for every tile, the (non-decreasing) sum of the earlier tiles of its run.
-template <int MT, typename S>
-__global__ __launch_bounds__(kUpdThreads) void k_tile_sums(UpdArgs a) {
+// A workgroup takes 4 consecutive runs of one job; wave r of the job owns the
+// tiles [r k, (r + 1) k).  It streams their cells once, evaluates f for every
+// request of the job, sums f over each tile in fp64 and records, per request
+// and tile, the (non-decreasing) sum of the earlier tiles of its run.
+template <int MT, typename S, int KR>
+__global__ __launch_bounds__(kUpdThreads) void k_tile_sums(BatchDev b) {
     extern __shared__ float tf_lds[];
-    load_tf(tf_lds, a.tf, a.tf_total);
-    const int M = fields_of<MT>(a);
-    const ImpCtx c = make_ctx(a);
     const int lane = lane_id();
-    const int64_t r = (int64_t)blockIdx.x * (kUpdThreads / kWave) + threadIdx.x / kWave;
-    if (r >= a.n_runs) return;
-    const int64_t t_begin = r * a.tiles_per_run;
-    const int64_t t_end = min(a.n_tiles, t_begin + a.tiles_per_run);
-    const int64_t c_begin = t_begin * kTileCells;
-    const int64_t c_end = min(a.n, t_end * kTileCells);
-    const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
+    const int wv = threadIdx.x / kWave;
+    int loaded = -1;
+    for (int64_t u = blockIdx.x; u < b.k1_units; u += gridDim.x) {
+        const int ji = find_job_k1(b, u);
+        const JobDev& j = b.jobs[ji];
+        if (ji != loaded) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < j.tf_total_all; i += blockDim.x) tf_lds[i] = j.tf_all[i];
+            __syncthreads();
+            loaded = ji;
+        }
+        const int M = fields_of<MT>(j.M);
+        const int nreq = KR == 1 ? 1 : j.n_req;
+        const int64_t r = (u - j.k1_unit0) * (kUpdThreads / kWave) + wv;
+        if (r >= j.n_runs) continue;
+        const ReqDev* rq = b.reqs + j.req0;
+        const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
+        const int64_t t_begin = r * j.tiles_per_run;
+        const int64_t t_end = min(j.n_tiles, t_begin + j.tiles_per_run);
+        const int64_t c_begin = t_begin * tile_cells;
+        const int64_t c_end = min(j.n, t_end * tile_cells);
+        const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
 
-    RunAcc run;
-    run.init();
-    double prev = 0.0;
-    double tacc = 0.0;
-    int64_t t = t_begin;
-    int in_tile = 0;
-    StepData<MT, S> cur;
-    cur.load(a, M, (c_begin >> 2) + lane);
-    for (int s = 0; s < nsteps; ++s) {
-        const int64_t quad = ((c_begin + (int64_t)s * kStepCells) >> 2) + lane;
-        StepData<MT, S> nxt;
-        if (s + 1 < nsteps) nxt.load(a, M, quad + kWave);
-        float f[4];
+        ImpCtx ctx[KR];
+        RunAcc run[KR];
+        double prev[KR], tacc[KR];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float x[MT];
+        for (int q = 0; q < KR; ++q) {
+            if (q < nreq) ctx[q] = make_ctx(rq[q]);
+            run[q].init();
+            prev[q] = 0.0;
+            tacc[q] = 0.0;
+        }
+        int64_t t = t_begin;
+        int in_tile = 0;
+        StepData<MT, S> cur;
+        cur.load(j, M, (c_begin >> 2) + lane);
+        for (int s = 0; s < nsteps; ++s) {
+            const int64_t quad = ((c_begin + (int64_t)s * kStepCells) >> 2) + lane;
+            StepData<MT, S> nxt;
+            if (s + 1 < nsteps) nxt.load(j, M, quad + kWave);
+            float x[MT][4];
 #pragma unroll
-            for (int m = 0; m < MT; ++m) x[m] = m < M ? cur.q[m].get(k) : 0.0f;
-            const float v = variation<MT>(x, M, tf_lds, a, c);
-            const float fk = importance_from_v(v, (cur.lv >> (8 * k)) & 0xFFu, c);
-            f[k] = ((quad << 2) + k < a.n) ? fk : 0.0f;
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int m = 0; m < MT; ++m) x[m][k] = m < M ? cur.q[m].get(k) : 0.0f;
+#pragma unroll
+            for (int q = 0; q < KR; ++q) {
+                if (q < nreq) {
+                    float f[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        float xk[MT];
+#pragma unroll
+                        for (int m = 0; m < MT; ++m) xk[m] = x[m][k];
+                        const float v = variation<MT>(xk, M, tf_lds + rq[q].tf_job_off, rq[q]);
+                        const float fk = importance_from_v(v, (cur.lv >> (8 * k)) & 0xFFu, ctx[q]);
+                        f[k] = ((quad << 2) + k < j.n) ? fk : 0.0f;
+                    }
+                    tacc[q] += (double)((f[0] + f[1]) + (f[2] + f[3]));
+                }
+            }
+            if (++in_tile == j.tile_steps || s + 1 == nsteps) {
+#pragma unroll
+                for (int q = 0; q < KR; ++q) {
+                    if (q < nreq) {
+                        const int mode = rq[q].scan_mode;
+                        const double ts = wave_sum_d(tacc[q]);
+                        tacc[q] = 0.0;
+                        prev[q] = fmax(prev[q], run[q].value(mode));
+                        if (lane == 0) rq[q].ws.local_prefix[t] = prev[q];
+                        run[q].add(mode, ts);
+                    }
+                }
+                ++t;
+                in_tile = 0;
+            }
+            cur = nxt;
         }
-        tacc += (double)((f[0] + f[1]) + (f[2] + f[3]));
-        if (++in_tile == kTileSteps || s + 1 == nsteps) {
-            const double ts = wave_sum_d(tacc);
-            tacc = 0.0;
-            prev = fmax(prev, run.value(a.scan_mode));
-            if (lane == 0) a.ws.local_prefix[t] = prev;
-            run.add(a.scan_mode, ts);
-            ++t;
-            in_tile = 0;
-        }
-        cur = nxt;
+#pragma unroll
+        for (int q = 0; q < KR; ++q)
+            if (q < nreq && lane == 0) rq[q].ws.run_total[r] = fmax(prev[q], run[q].value(rq[q].scan_mode));
     }
-    if (lane == 0) a.ws.run_total[r] = fmax(prev, run.value(a.scan_mode));
 }
 
 // ------------------------------------------------------------------ K2
@@ -270,7 +361,6 @@ struct AccF64 {
     __device__ static AccF64 combine(const AccF64& a, const AccF64& b) { return {a.v + b.v}; }
     __device__ double value() const { return v; }
     __device__ AccF64 shfl_up(int d) const { return {shfl_up_d(v, d)}; }
-    __device__ AccF64 lane(int l) const { return {readlane(v, l)}; }
 };
 
 // compensated fp32: unevaluated sum hi + lo, error-free TwoSum on every add
@@ -299,7 +389,6 @@ struct AccKahan32 {
     }
     __device__ double value() const { return (double)hi + (double)lo; }
     __device__ AccKahan32 shfl_up(int d) const { return {shfl_up_f(hi, d), shfl_up_f(lo, d)}; }
-    __device__ AccKahan32 lane(int l) const { return {readlane(hi, l), readlane(lo, l)}; }
 };
 
 struct AccF32 {
@@ -309,7 +398,6 @@ struct AccF32 {
     __device__ static AccF32 combine(const AccF32& a, const AccF32& b) { return {a.v + b.v}; }
     __device__ double value() const { return (double)v; }
     __device__ AccF32 shfl_up(int d) const { return {shfl_up_f(v, d)}; }
-    __device__ AccF32 lane(int l) const { return {readlane(v, l)}; }
 };
 
 constexpr int kCarryThreads = 1024;
@@ -317,33 +405,30 @@ constexpr int kCarryItems = 8;                              // run totals per th
 constexpr int kCarryRound = kCarryThreads * kCarryItems;
 constexpr int kCarryWaves = kCarryThreads / kWave;
 
-// run_base[r] = sum of the run totals before r, run_base[R] = F_tot.  One
-// workgroup walks the run totals in rounds of 8192: a sequential prefix over
-// each thread's 8 values, a wave scan of the thread totals made monotone by a
-// running maximum, and sequential wave and round bases; every base is clamped
-// to the next thread's base, so the bases never decrease.
+// One workgroup per request.  run_base[r] = sum of the run totals before r,
+// run_base[R] = F_tot: a sequential prefix over each thread's 8 totals, a
+// wave scan of the thread totals made monotone by a running maximum, and
+// sequential wave and round bases; every base is clamped to the next thread's
+// base, so the bases never decrease.
 template <typename Acc>
-__global__ __launch_bounds__(kCarryThreads) void k_carry(UpdArgs a) {
+__device__ void carry_scan(const ReqDev& q, int64_t T, int64_t n_cells) {
     __shared__ double wave_base[kCarryWaves + 1];
     __shared__ Acc wave_acc[kCarryWaves];
     __shared__ Acc round_acc;
     __shared__ double round_end;
-    const int64_t T = a.n_runs;
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-    const double* ts = a.ws.run_total;
-    double* carry = a.ws.run_base;
+    const double* ts = q.ws.run_total;
+    double* base_out = q.ws.run_base;
     if (tid == 0) {
         round_acc = Acc::zero();
         round_end = 0.0;
     }
     __syncthreads();
-
     for (int64_t r0 = 0; r0 < T; r0 += kCarryRound) {
         const int64_t b0 = r0 + (int64_t)tid * kCarryItems;
         double v[kCarryItems];
 #pragma unroll
         for (int k = 0; k < kCarryItems; ++k) v[k] = (b0 + k < T) ? ts[b0 + k] : 0.0;
-        // thread-sequential prefix in the chosen arithmetic
         Acc pre[kCarryItems];
         Acc run = Acc::zero();
 #pragma unroll
@@ -351,7 +436,6 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(UpdArgs a) {
             pre[k] = run;
             run.add(v[k]);
         }
-        // inclusive wave scan of the thread totals
         Acc inc = run;
         for (int d = 1; d < kWave; d <<= 1) {
             const Acc o = inc.shfl_up(d);
@@ -360,13 +444,12 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(UpdArgs a) {
         if (lane == kWave - 1) wave_acc[w] = inc;
         __syncthreads();
         if (tid == 0) {
-            // sequential over the waves: non-decreasing wave bases
             Acc base = round_acc;
             double prev = round_end;
-            for (int q = 0; q < kCarryWaves; ++q) {
+            for (int k = 0; k < kCarryWaves; ++k) {
                 prev = fmax(prev, base.value());
-                wave_base[q] = prev;
-                base = Acc::combine(base, wave_acc[q]);
+                wave_base[k] = prev;
+                base = Acc::combine(base, wave_acc[k]);
             }
             prev = fmax(prev, base.value());
             wave_base[kCarryWaves] = prev;
@@ -374,8 +457,6 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(UpdArgs a) {
             round_acc = base;
         }
         __syncthreads();
-        // thread base = wave base + exclusive wave prefix, kept inside the
-        // wave's range and made non-decreasing by a running maximum
         const double wb = wave_base[w], wn = wave_base[w + 1];
         const Acc exc = inc.shfl_up(1);
         double tb = lane == 0 ? wb : fmin(fmax(wb + exc.value(), wb), wn);
@@ -383,7 +464,6 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(UpdArgs a) {
             const double o = shfl_up_d(tb, d);
             if (lane >= d) tb = fmax(tb, o);
         }
-        // the next thread's base bounds this thread's carries
         const int src = lane + 1 < kWave ? lane + 1 : lane;
         const uint64_t u = __double_as_longlong(tb);
         const int nlo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)u);
@@ -394,21 +474,29 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(UpdArgs a) {
 #pragma unroll
         for (int k = 0; k < kCarryItems; ++k) {
             c = fmax(c, fmin(tb + pre[k].value(), nb));
-            if (b0 + k < T) carry[b0 + k] = c;
+            if (b0 + k < T) base_out[b0 + k] = c;
         }
         __syncthreads();
     }
-    if (tid == 0) carry[T] = round_end;
-    __syncthreads();
-
-    // a zero total means every f was zero: fall back to f = 1 (linear map;
-    // the projection then derives the tile offsets from the cell counts)
-    const double F = carry[T];
-    const bool degenerate = !(F > 0.0);
     if (tid == 0) {
-        a.ws.scal[0] = degenerate ? (double)a.n : F;
-        a.ws.scal[1] = degenerate ? 1.0 : 0.0;
+        base_out[T] = round_end;
+        // a zero total means every f was zero: fall back to f = 1 (linear map;
+        // the projection then derives the tile offsets from the cell counts)
+        const bool degenerate = !(round_end > 0.0);
+        q.ws.scal[0] = degenerate ? (double)n_cells : round_end;
+        q.ws.scal[1] = degenerate ? 1.0 : 0.0;
     }
+}
+
+__global__ __launch_bounds__(kCarryThreads) void k_carry(BatchDev b) {
+    const ReqDev& q = b.reqs[blockIdx.x];
+    const JobDev& j = b.jobs[q.job];
+    if (q.scan_mode == DVL_SCAN_KAHAN_FP32)
+        carry_scan<AccKahan32>(q, j.n_runs, j.n);
+    else if (q.scan_mode == DVL_SCAN_NAIVE_FP32)
+        carry_scan<AccF32>(q, j.n_runs, j.n);
+    else
+        carry_scan<AccF64>(q, j.n_runs, j.n);
 }
 
 // ------------------------------------------------------------------ K3 helpers
@@ -465,21 +553,22 @@ __device__ __forceinline__ int wave_min_i32(int v) {
     return v;
 }
 
-
 // Sum of the importance of all tiles before tile t (t = T gives F_tot): the
 // run's base plus the tile's prefix inside its run, never above the next
 // run's base.  One definition serves both neighbours of every tile boundary,
 // and the offsets never decrease.
-__device__ __forceinline__ double tile_offset(const UpdArgs& a, int64_t t, bool degenerate) {
-    if (degenerate) return t >= a.n_tiles ? (double)a.n : (double)(t * kTileCells);
-    if (t >= a.n_tiles) return a.ws.run_base[a.n_runs];
-    const int64_t r = t / a.tiles_per_run;
-    const double lo = a.ws.run_base[r], hi = a.ws.run_base[r + 1];
-    return fmin(fmax(lo + a.ws.local_prefix[t], lo), hi);
+__device__ __forceinline__ double tile_offset(const JobDev& j, const UpdWorkspace& ws, int64_t t,
+                                              bool degenerate) {
+    const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
+    if (degenerate) return t >= j.n_tiles ? (double)j.n : (double)(t * tile_cells);
+    if (t >= j.n_tiles) return ws.run_base[j.n_runs];
+    const int64_t r = t / j.tiles_per_run;
+    const double lo = ws.run_base[r], hi = ws.run_base[r + 1];
+    return fmin(fmax(lo + ws.local_prefix[t], lo), hi);
 }
 
-// Per-wave LDS scratch of the bin reductions: the partial statistics of up to
-// kRedFields fields for the 64 lanes, then the reduced values.
+// LDS scratch of the bin reductions of one wave: the partial statistics of up
+// to kRedFields fields for the 64 lanes, then the reduced values.
 constexpr int kRedFields = 4;
 struct RedScratch {
     double sum[kRedFields][kWave];
@@ -494,24 +583,24 @@ constexpr size_t kRedBytes = sizeof(RedScratch);
 // Reduce the per-lane partials (asum, amin, amax) of one bin over the wave
 // and store the bin: a complete bin (dest 0) gets its final mean, min, max
 // and height; a tile-edge bin goes to the tile's head (dest 1) or tail
-// (dest 2) record.  Fields are taken kRedFields at a time; lane j < 3 * F
-// reduces one column in lane order, lanes m < F finalise field m.
+// (dest 2) record.  Fields are taken kRedFields at a time; lane j < F reduces
+// the sums of field j in lane order, lanes 16 + j and 32 + j its minima and
+// maxima, and lanes m < F finalise field m.
 template <int MT>
-__device__ void close_bin(const UpdArgs& a, int M, RedScratch* rs, int dest, int64_t t, int key,
+__device__ void close_bin(const ReqDev& q, int M, int64_t T, RedScratch* rs, int dest, int64_t t, int key,
                           uint32_t first, uint32_t last, const double (&asum)[MT],
                           const float (&amin)[MT], const float (&amax)[MT], const float* tf) {
     const int lane = lane_id();
     const uint32_t cnt = last - first + 1u;
-    const int64_t T = a.n_tiles;
 #pragma unroll
     for (int m0 = 0; m0 < MT; m0 += kRedFields) {
         if (m0 >= M) break;
 #pragma unroll
-        for (int j = 0; j < kRedFields; ++j) {
-            if (m0 + j < MT) {
-                rs->sum[j][lane] = asum[m0 + j];
-                rs->mn[j][lane] = amin[m0 + j];
-                rs->mx[j][lane] = amax[m0 + j];
+        for (int jj = 0; jj < kRedFields; ++jj) {
+            if (m0 + jj < MT) {
+                rs->sum[jj][lane] = asum[m0 + jj];
+                rs->mn[jj][lane] = amin[m0 + jj];
+                rs->mx[jj][lane] = amax[m0 + jj];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -528,15 +617,15 @@ __device__ void close_bin(const UpdArgs& a, int M, RedScratch* rs, int dest, int
             }
             rs->rsum[lane] = (s0 + s1) + (s2 + s3);
         } else if (lane >= 16 && lane < 16 + nf) {
-            const int j = lane - 16;
+            const int jj = lane - 16;
             float v = INFINITY;
-            for (int l = 0; l < kWave; ++l) v = fminf(v, rs->mn[j][l]);
-            rs->rmn[j] = v;
+            for (int l = 0; l < kWave; ++l) v = fminf(v, rs->mn[jj][l]);
+            rs->rmn[jj] = v;
         } else if (lane >= 32 && lane < 32 + nf) {
-            const int j = lane - 32;
+            const int jj = lane - 32;
             float v = -INFINITY;
-            for (int l = 0; l < kWave; ++l) v = fmaxf(v, rs->mx[j][l]);
-            rs->rmx[j] = v;
+            for (int l = 0; l < kWave; ++l) v = fmaxf(v, rs->mx[jj][l]);
+            rs->rmx[jj] = v;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -547,76 +636,79 @@ __device__ void close_bin(const UpdArgs& a, int M, RedScratch* rs, int dest, int
             const float mn = rs->rmn[lane], mx = rs->rmx[lane];
             if (dest == 0) {
                 const float mean = (float)(sm / (double)cnt);
-                const int e = tf_entry(mean, a.s[m], a.b[m], a.nmax[m]);
-                const int64_t o = (int64_t)m * a.W + key;
-                a.mean[o] = mean;
-                a.vmin[o] = mn;
-                a.vmax[o] = mx;
-                a.y[o] = tf[a.tf_off[m] + e];
+                const int e = tf_entry(mean, q.s[m], q.b[m], q.nmax[m]);
+                const int64_t o = (int64_t)m * q.W + key;
+                q.mean[o] = mean;
+                q.vmin[o] = mn;
+                q.vmax[o] = mx;
+                q.y[o] = tf[q.tf_off[m] + e];
             } else {
                 const int64_t o = ((int64_t)(dest - 1) * M + m) * T + t;
-                a.ws.rec_sum[o] = sm;
-                a.ws.rec_min[o] = mn;
-                a.ws.rec_max[o] = mx;
+                q.ws.rec_sum[o] = sm;
+                q.ws.rec_min[o] = mn;
+                q.ws.rec_max[o] = mx;
             }
         }
         __builtin_amdgcn_wave_barrier();
     }
     if (lane == 0) {
         if (dest == 0) {
-            a.first_cell[key] = first;
-            a.last_cell[key] = last;
+            q.first_cell[key] = first;
+            q.last_cell[key] = last;
         } else {
-            a.ws.rec_first[(dest - 1) * T + t] = first;
-            a.ws.rec_last[(dest - 1) * T + t] = last;
+            q.ws.rec_first[(dest - 1) * T + t] = first;
+            q.ws.rec_last[(dest - 1) * T + t] = last;
         }
     }
 }
 
 // a bin that holds one cell only (strictly inside a wide cell)
 template <int MT>
-__device__ void write_single(const UpdArgs& a, int M, int key, const float (&x)[MT], uint32_t g,
-                             const float* tf) {
-    a.first_cell[key] = g;
-    a.last_cell[key] = g;
+__device__ void write_single(const ReqDev& q, int M, int key, const float (&x)[MT], uint32_t g, const float* tf) {
+    q.first_cell[key] = g;
+    q.last_cell[key] = g;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         if (m < M) {
-            const int e = tf_entry(x[m], a.s[m], a.b[m], a.nmax[m]);
-            const int64_t o = (int64_t)m * a.W + key;
-            a.mean[o] = x[m];
-            a.vmin[o] = x[m];
-            a.vmax[o] = x[m];
-            a.y[o] = tf[a.tf_off[m] + e];
+            const int e = tf_entry(x[m], q.s[m], q.b[m], q.nmax[m]);
+            const int64_t o = (int64_t)m * q.W + key;
+            q.mean[o] = x[m];
+            q.vmin[o] = x[m];
+            q.vmax[o] = x[m];
+            q.y[o] = tf[q.tf_off[m] + e];
         }
     }
 }
 
 // ------------------------------------------------------------------ K3
 
-template <int MT, typename S>
-__global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
-    extern __shared__ float tf_lds[];
-    load_tf(tf_lds, a.tf, a.tf_total);
-    RedScratch* rs = reinterpret_cast<RedScratch*>(
-        reinterpret_cast<char*>(tf_lds) + ((size_t)a.tf_total * sizeof(float) + 15) / 16 * 16) +
-        threadIdx.x / kWave;
-    const int M = fields_of<MT>(a);
-    const ImpCtx c = make_ctx(a);
-    const bool degenerate = a.ws.scal[1] != 0.0;
-    const double Ftot = a.ws.scal[0];
-    const double scale_d = (double)a.W / Ftot;
-    const float scale_f = (float)scale_d;
-    const int W1 = a.W - 1;
-    const int lane = lane_id();
-    const int64_t wave = (int64_t)blockIdx.x * (kUpdThreads / kWave) + threadIdx.x / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * (kUpdThreads / kWave);
+constexpr int kBinThreads = 64;   // one wave per workgroup: each unit is one (request, tile)
 
-    for (int64_t t = wave; t < a.n_tiles; t += nwaves) {
-        const int64_t tbase = t * kTileCells;
-        const float X0 = (float)(tile_offset(a, t, degenerate) * scale_d);
-        const float X1 = (float)(tile_offset(a, t + 1, degenerate) * scale_d);
-        const int64_t tend = min(tbase + (int64_t)kTileCells, a.n);
+template <int MT, typename S>
+__global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
+    extern __shared__ float lds[];
+    RedScratch* rs = reinterpret_cast<RedScratch*>(lds);
+    float* tf_lds = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + (kRedBytes + 15) / 16 * 16);
+    const int lane = lane_id();
+    int loaded = -1;
+
+    for (int64_t u = blockIdx.x; u < bd.k3_units; u += gridDim.x) {
+        const int qi = find_req_k3(bd, u);
+        const ReqDev& q = bd.reqs[qi];
+        const JobDev& j = bd.jobs[q.job];
+        const int64_t t = u - q.k3_unit0;
+        const int M = fields_of<MT>(j.M);
+        const int64_t T = j.n_tiles;
+        const bool degenerate = q.ws.scal[1] != 0.0;
+        const double Ftot = q.ws.scal[0];
+        const double scale_d = (double)q.W / Ftot;
+        const float scale_f = (float)scale_d;
+        const int W1 = q.W - 1;
+        const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
+        const int64_t tbase = t * tile_cells;
+        const float X0 = (float)(tile_offset(j, q.ws, t, degenerate) * scale_d);
+        const float X1 = (float)(tile_offset(j, q.ws, t + 1, degenerate) * scale_d);
+        const int64_t tend = min(tbase + tile_cells, j.n);
         const uint32_t last_valid = (uint32_t)(tend - 1);
         const int nsteps = (int)((tend - tbase + kStepCells - 1) / kStepCells);
 
@@ -627,20 +719,30 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
         const int b1 = max(0, min((int)floorf(X1), W1));
         if (b0 == b1) {
             if (lane < M) {
-                const int64_t src = (int64_t)lane * a.n_tiles + t;
-                const int64_t dst = (int64_t)lane * a.n_tiles + t;   // head record
-                a.ws.rec_sum[dst] = a.agg_sum[src];
-                a.ws.rec_min[dst] = a.agg_min[src];
-                a.ws.rec_max[dst] = a.agg_max[src];
+                const int64_t o = (int64_t)lane * T + t;   // head record of field `lane`
+                q.ws.rec_sum[o] = j.agg_sum[o];
+                q.ws.rec_min[o] = j.agg_min[o];
+                q.ws.rec_max[o] = j.agg_max[o];
             }
             if (lane == 0) {
-                a.ws.rec_first[t] = (uint32_t)tbase;
-                a.ws.rec_last[t] = last_valid;
-                a.ws.head_bin[t] = b0;
-                a.ws.tail_bin[t] = b0;
+                q.ws.rec_first[t] = (uint32_t)tbase;
+                q.ws.rec_last[t] = last_valid;
+                q.ws.head_bin[t] = b0;
+                q.ws.tail_bin[t] = b0;
             }
             continue;
         }
+
+        // the tile is rescanned: this request's tables in LDS
+        if (qi != loaded) {
+            __builtin_amdgcn_wave_barrier();
+            for (int i = lane; i < q.tf_total; i += kWave) tf_lds[i] = q.tf[i];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            loaded = qi;
+        }
+        const ImpCtx c = make_ctx(q);
 
         float run = 0.0f;
         bool o_valid = false;
@@ -656,12 +758,12 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
         }
 
         StepData<MT, S> cur;
-        cur.load(a, M, (tbase >> 2) + lane);
+        cur.load(j, M, (tbase >> 2) + lane);
         for (int s = 0; s < nsteps; ++s) {
             const int64_t c0 = tbase + (int64_t)s * kStepCells;
             const int64_t quad = (c0 >> 2) + lane;
             StepData<MT, S> nxt;
-            if (s + 1 < nsteps) nxt.load(a, M, quad + kWave);
+            if (s + 1 < nsteps) nxt.load(j, M, quad + kWave);
 
             float x[MT][4];
             float f[4];
@@ -676,9 +778,9 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
                     x[m][k] = xk[m];
                 }
                 g[k] = (uint32_t)((quad << 2) + k);
-                valid[k] = (int64_t)g[k] < a.n;
+                valid[k] = (int64_t)g[k] < j.n;
                 float fk = 1.0f;
-                if (!degenerate) fk = importance_from_v(variation<MT>(xk, M, tf_lds, a, c),
+                if (!degenerate) fk = importance_from_v(variation<MT>(xk, M, tf_lds, q),
                                                         (cur.lv >> (8 * k)) & 0xFFu, c);
                 f[k] = valid[k] ? fk : 0.0f;
             }
@@ -706,7 +808,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
                 bhi[k] = max(blo[k], min((int)ceilf(en) - 1, W1));
             }
 
-            const bool full = c0 + kStepCells <= a.n;
+            const bool full = c0 + kStepCells <= j.n;
             const int key0 = readlane(blo[0], 0);
             if (s == 0) Bh = key0;
             const int key_end = full ? readlane(bhi[3], kWave - 1) : INT_MAX;
@@ -733,13 +835,13 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
             }
 
             // ---- bin boundary inside the step ----
-            const int last_lane = full ? kWave - 1 : (int)((a.n - 1 - c0) >> 2);
-            const int kl = (int)((a.n - 1 - c0) & 3);
+            const int last_lane = full ? kWave - 1 : (int)((j.n - 1 - c0) >> 2);
+            const int kl = (int)((j.n - 1 - c0) & 3);
             const int bhi_last = kl == 0 ? bhi[0] : (kl == 1 ? bhi[1] : (kl == 2 ? bhi[2] : bhi[3]));
             const int key_last = full ? key_end : readlane(bhi_last, last_lane);
             // (1) the open bin ended with the previous step: reduce and emit it
             if (o_valid && key0 != O) {
-                close_bin<MT>(a, M, rs, O == Bh ? 1 : 0, t, O, O_first, O_last, asum, amin, amax, tf_lds);
+                close_bin<MT>(q, M, T, rs, O == Bh ? 1 : 0, t, O, O_first, O_last, asum, amin, amax, tf_lds);
                 o_valid = false;
             }
             // (2) bins strictly inside a wide cell hold that cell alone
@@ -749,14 +851,13 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
                     float xk[MT];
 #pragma unroll
                     for (int m = 0; m < MT; ++m) xk[m] = x[m][k];
-                    for (int b = blo[k] + 1; b < bhi[k]; ++b) write_single<MT>(a, M, b, xk, g[k], tf_lds);
+                    for (int bb = blo[k] + 1; bb < bhi[k]; ++bb) write_single<MT>(q, M, bb, xk, g[k], tf_lds);
                 }
             }
             // (3) every bin that is the first or last bin of some cell of this
             //     step, in increasing order; all but the step's last one close
             int b = key0;
             while (true) {
-                // this lane's cells in bin b (first or last bin of the cell)
                 bool in[4];
                 uint32_t gmin = 0xFFFFFFFFu, gmax = 0u;
 #pragma unroll
@@ -796,14 +897,13 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
                     // stays open into the next step (per-lane accumulators keep it)
                     O = b;
                     O_first = bfirst;
-                    O_last = (uint32_t)min((int64_t)c0 + kStepCells - 1, a.n - 1);
+                    O_last = (uint32_t)min((int64_t)c0 + kStepCells - 1, j.n - 1);
                     o_valid = true;
                     break;
                 }
-                close_bin<MT>(a, M, rs, b == Bh ? 1 : 0, t, b, bfirst, wave_max_u32(gmax), asum, amin, amax,
+                close_bin<MT>(q, M, T, rs, b == Bh ? 1 : 0, t, b, bfirst, wave_max_u32(gmax), asum, amin, amax,
                               tf_lds);
                 o_valid = false;
-                // next key of this step above b
                 int nk = INT_MAX;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -820,10 +920,10 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
 
         // tile end: the open bin is the tile's last bin
         if (o_valid) {
-            close_bin<MT>(a, M, rs, O == Bh ? 1 : 2, t, O, O_first, O_last, asum, amin, amax, tf_lds);
+            close_bin<MT>(q, M, T, rs, O == Bh ? 1 : 2, t, O, O_first, O_last, asum, amin, amax, tf_lds);
             if (lane == 0) {
-                a.ws.head_bin[t] = Bh;
-                a.ws.tail_bin[t] = O;
+                q.ws.head_bin[t] = Bh;
+                q.ws.tail_bin[t] = O;
             }
         }
     }
@@ -832,18 +932,22 @@ __global__ __launch_bounds__(kUpdThreads) void k_bin(UpdArgs a) {
 // ------------------------------------------------------------------ K4
 
 template <int MT>
-__global__ __launch_bounds__(256) void k_edges(UpdArgs a) {
-    const int M = fields_of<MT>(a);
+__global__ __launch_bounds__(256) void k_edges(BatchDev bd) {
     const int lane = lane_id();
-    const int b = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *a.f_total = a.ws.scal[0];
-        *a.vmax_used = *a.vmax_dev;
+    const int64_t u = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    if (u >= bd.k4_units) return;
+    const int qi = find_req_k4(bd, u);
+    const ReqDev& q = bd.reqs[qi];
+    const JobDev& j = bd.jobs[q.job];
+    const int M = fields_of<MT>(j.M);
+    const int b = (int)(u - q.k4_unit0);
+    if (b == 0 && lane == 0) {
+        *q.f_total = q.ws.scal[0];
+        *q.vmax_used = *q.vmax_dev;
     }
-    if (b >= a.W) return;
-    const int64_t T = a.n_tiles;
-    const int32_t* hb = a.ws.head_bin;
-    const int32_t* tb = a.ws.tail_bin;
+    const int64_t T = j.n_tiles;
+    const int32_t* hb = q.ws.head_bin;
+    const int32_t* tb = q.ws.tail_bin;
     // tiles touching bin b: t0 = first with tail >= b, t1 = last with head <= b
     int64_t lo = 0, hi = T;
     while (lo < hi) {
@@ -858,7 +962,7 @@ __global__ __launch_bounds__(256) void k_edges(UpdArgs a) {
         if (hb[mid] <= b) lo = mid + 1; else hi = mid;
     }
     const int64_t t1 = lo - 1;
-    if (t0 <= t1 && t0 == t1 && hb[t0] < b && b < tb[t0]) return;  // finalised by K3
+    if (t0 <= t1 && t0 == t1 && hb[t0] < b && b < tb[t0]) return;  // finalised by the projection pass
 
     Seg<MT> acc;
     seg_clear(acc);
@@ -866,15 +970,15 @@ __global__ __launch_bounds__(256) void k_edges(UpdArgs a) {
         const int r = hb[t] == b ? 0 : (tb[t] == b ? 1 : -1);
         if (r < 0) continue;
         Seg<MT> s;
-        s.first = a.ws.rec_first[r * T + t];
-        s.last = a.ws.rec_last[r * T + t];
+        s.first = q.ws.rec_first[r * T + t];
+        s.last = q.ws.rec_last[r * T + t];
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             if (m < M) {
                 const int64_t o = ((int64_t)r * M + m) * T + t;
-                s.sum[m] = a.ws.rec_sum[o];
-                s.mn[m] = a.ws.rec_min[o];
-                s.mx[m] = a.ws.rec_max[o];
+                s.sum[m] = q.ws.rec_sum[o];
+                s.mn[m] = q.ws.rec_min[o];
+                s.mx[m] = q.ws.rec_max[o];
             } else {
                 s.sum[m] = 0.0;
                 s.mn[m] = INFINITY;
@@ -890,54 +994,52 @@ __global__ __launch_bounds__(256) void k_edges(UpdArgs a) {
         acc.mn[m] = wave_min_f(acc.mn[m]);
         acc.mx[m] = wave_max_f(acc.mx[m]);
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        acc.first = min(acc.first, (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ o) << 2, (int)acc.first));
-        acc.last = max(acc.last, (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ o) << 2, (int)acc.last));
-    }
+    acc.first = wave_min_u32(acc.first);
+    acc.last = wave_max_u32(acc.last);
     if (lane != 0) return;
     if (acc.first == 0xFFFFFFFFu) {  // no cell (cannot happen with a positive total width)
-        a.first_cell[b] = 0xFFFFFFFFu;
-        a.last_cell[b] = 0xFFFFFFFEu;
+        q.first_cell[b] = 0xFFFFFFFFu;
+        q.last_cell[b] = 0xFFFFFFFEu;
         for (int m = 0; m < M; ++m) {
-            const int64_t o = (int64_t)m * a.W + b;
-            a.mean[o] = 0.0f;
-            a.vmin[o] = INFINITY;
-            a.vmax[o] = -INFINITY;
-            a.y[o] = 0.0f;
+            const int64_t o = (int64_t)m * q.W + b;
+            q.mean[o] = 0.0f;
+            q.vmin[o] = INFINITY;
+            q.vmax[o] = -INFINITY;
+            q.y[o] = 0.0f;
         }
         return;
     }
     const uint32_t cnt = acc.last - acc.first + 1u;
-    a.first_cell[b] = acc.first;
-    a.last_cell[b] = acc.last;
+    q.first_cell[b] = acc.first;
+    q.last_cell[b] = acc.last;
     for (int m = 0; m < M; ++m) {
         const float mean = (float)(acc.sum[m] / (double)cnt);
-        const int e = tf_entry(mean, a.s[m], a.b[m], a.nmax[m]);
-        const int64_t o = (int64_t)m * a.W + b;
-        a.mean[o] = mean;
-        a.vmin[o] = acc.mn[m];
-        a.vmax[o] = acc.mx[m];
-        a.y[o] = a.tf[a.tf_off[m] + e];
+        const int e = tf_entry(mean, q.s[m], q.b[m], q.nmax[m]);
+        const int64_t o = (int64_t)m * q.W + b;
+        q.mean[o] = mean;
+        q.vmin[o] = acc.mn[m];
+        q.vmax[o] = acc.mx[m];
+        q.y[o] = q.tf[q.tf_off[m] + e];
     }
 }
 
-
 // ------------------------------------------------------------------ per-tile statistics
 
-// sum / min / max of one sorted field over every 4096-cell tile; one wave per
-// tile (computed once per volume and per data change, not per update)
+// sum / min / max of one sorted field over every tile; one wave per tile
+// (computed once per volume and per data change, not per update)
 template <typename S>
 __global__ __launch_bounds__(kUpdThreads) void k_tile_aggregates(int64_t n, const void* __restrict__ field,
-                                                                 int64_t n_tiles, double* __restrict__ sum,
+                                                                 int64_t n_tiles, int tile_steps,
+                                                                 double* __restrict__ sum,
                                                                  float* __restrict__ mn, float* __restrict__ mx) {
     const int lane = lane_id();
     const int64_t wave = (int64_t)blockIdx.x * (kUpdThreads / kWave) + threadIdx.x / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * (kUpdThreads / kWave);
     for (int64_t t = wave; t < n_tiles; t += nwaves) {
-        const int64_t tbase = t * kTileCells;
+        const int64_t tbase = t * tile_steps * (int64_t)kStepCells;
         double acc = 0.0;
         float lo = INFINITY, hi = -INFINITY;
-        for (int st = 0; st < kTileSteps; ++st) {
+        for (int st = 0; st < tile_steps; ++st) {
             const int64_t quad = ((tbase + (int64_t)st * kStepCells) >> 2) + lane;
             Quad<S> q;
             q.load(field, quad);
@@ -964,78 +1066,82 @@ __global__ __launch_bounds__(kUpdThreads) void k_tile_aggregates(int64_t n, cons
     }
 }
 
-dvl_status launch_tile_aggregates(int64_t n, int dtype, const void* field, int64_t n_tiles, double* sum,
-                                  float* mn, float* mx, int n_cu, hipStream_t s) {
+dvl_status launch_tile_aggregates(int64_t n, int dtype, const void* field, int64_t n_tiles, int tile_steps,
+                                  double* sum, float* mn, float* mx, int n_cu, hipStream_t s) {
     const int64_t wg_needed = (n_tiles + (kUpdThreads / kWave) - 1) / (kUpdThreads / kWave);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(wg_needed, (int64_t)n_cu * 8));
     if (dtype == DVL_F16)
-        hipLaunchKernelGGL(k_tile_aggregates<F16>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles, sum, mn, mx);
+        hipLaunchKernelGGL(k_tile_aggregates<F16>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles,
+                           tile_steps, sum, mn, mx);
     else if (dtype == DVL_BF16)
-        hipLaunchKernelGGL(k_tile_aggregates<BF16>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles, sum, mn, mx);
+        hipLaunchKernelGGL(k_tile_aggregates<BF16>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles,
+                           tile_steps, sum, mn, mx);
     else
-        hipLaunchKernelGGL(k_tile_aggregates<F32>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles, sum, mn, mx);
+        hipLaunchKernelGGL(k_tile_aggregates<F32>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles,
+                           tile_steps, sum, mn, mx);
     DVL_HIP(hipGetLastError());
     return DVL_OK;
 }
 
 // ------------------------------------------------------------------ launcher
 
-template <int MT, typename S>
-static dvl_status launch_typed(const UpdArgs& a, int n_cu, hipStream_t s, hipEvent_t* ev) {
-    const size_t lds = (size_t)a.tf_total * sizeof(float);
-    const int64_t wg_needed = (a.n_tiles + (kUpdThreads / kWave) - 1) / (kUpdThreads / kWave);
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(wg_needed, (int64_t)n_cu * 8));
+template <int MT, typename S, int KR>
+static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEvent_t* ev) {
     auto mark = [&](int i) -> dvl_status {
         if (ev) DVL_HIP(hipEventRecord(ev[i], s));
         return DVL_OK;
     };
+    const size_t lds1 = (size_t)b.max_job_tf * sizeof(float);
+    const unsigned g1 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.k1_units, (int64_t)n_cu * 8));
     if (dvl_status st = mark(0)) return st;
-    if (a.vmax_exact) {
-        hipLaunchKernelGGL((k_vmax_exact<MT, S>), dim3(grid), dim3(kUpdThreads), lds, s, a);
+    if (b.any_exact) {
+        hipLaunchKernelGGL((k_vmax_exact<MT, S, KR>), dim3(g1), dim3(kUpdThreads), lds1, s, b);
         DVL_HIP(hipGetLastError());
     }
     if (dvl_status st = mark(1)) return st;
-    const unsigned grid_runs = (unsigned)std::max<int64_t>(1, (a.n_runs + (kUpdThreads / kWave) - 1) / (kUpdThreads / kWave));
-    hipLaunchKernelGGL((k_tile_sums<MT, S>), dim3(grid_runs), dim3(kUpdThreads), lds, s, a);
+    hipLaunchKernelGGL((k_tile_sums<MT, S, KR>), dim3(g1), dim3(kUpdThreads), lds1, s, b);
     DVL_HIP(hipGetLastError());
     if (dvl_status st = mark(2)) return st;
-    if (a.scan_mode == DVL_SCAN_KAHAN_FP32)
-        hipLaunchKernelGGL(k_carry<AccKahan32>, dim3(1), dim3(kCarryThreads), 0, s, a);
-    else if (a.scan_mode == DVL_SCAN_NAIVE_FP32)
-        hipLaunchKernelGGL(k_carry<AccF32>, dim3(1), dim3(kCarryThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_carry<AccF64>, dim3(1), dim3(kCarryThreads), 0, s, a);
+    hipLaunchKernelGGL(k_carry, dim3((unsigned)b.n_reqs), dim3(kCarryThreads), 0, s, b);
     DVL_HIP(hipGetLastError());
     if (dvl_status st = mark(3)) return st;
-    const size_t lds_bin = ((size_t)a.tf_total * sizeof(float) + 15) / 16 * 16 + (kUpdThreads / kWave) * kRedBytes;
-    hipLaunchKernelGGL((k_bin<MT, S>), dim3(grid), dim3(kUpdThreads), lds_bin, s, a);
+    const size_t lds3 = (kRedBytes + 15) / 16 * 16 + (size_t)b.max_req_tf * sizeof(float);
+    const unsigned g3 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.k3_units, (int64_t)n_cu * 16));
+    hipLaunchKernelGGL((k_bin<MT, S>), dim3(g3), dim3(kBinThreads), lds3, s, b);
     DVL_HIP(hipGetLastError());
     if (dvl_status st = mark(4)) return st;
-    const unsigned g4 = (unsigned)((a.W + 3) / 4);
-    hipLaunchKernelGGL((k_edges<MT>), dim3(g4), dim3(256), 0, s, a);
+    const unsigned g4 = (unsigned)std::max<int64_t>(1, (b.k4_units + 3) / 4);
+    hipLaunchKernelGGL((k_edges<MT>), dim3(g4), dim3(256), 0, s, b);
     DVL_HIP(hipGetLastError());
     return mark(5);
 }
 
-template <typename S>
-static dvl_status launch_m(const UpdArgs& a, int n_cu, hipStream_t s, hipEvent_t* ev) {
-    switch (a.M) {
-        case 1: return launch_typed<1, S>(a, n_cu, s, ev);
-        case 2: return launch_typed<2, S>(a, n_cu, s, ev);
-        case 3: return launch_typed<3, S>(a, n_cu, s, ev);
-        case 4: return launch_typed<4, S>(a, n_cu, s, ev);
-        case 5: return launch_typed<5, S>(a, n_cu, s, ev);
-        case 6: return launch_typed<6, S>(a, n_cu, s, ev);
-        case 7: return launch_typed<7, S>(a, n_cu, s, ev);
-        case 8: return launch_typed<8, S>(a, n_cu, s, ev);
-        default: return launch_typed<16, S>(a, n_cu, s, ev);
+template <typename S, int KR>
+static dvl_status launch_m(const BatchDev& b, int max_m, int n_cu, hipStream_t s, hipEvent_t* ev) {
+    switch (max_m) {
+        case 1: return launch_typed<1, S, KR>(b, n_cu, s, ev);
+        case 2: return launch_typed<2, S, KR>(b, n_cu, s, ev);
+        case 3: return launch_typed<3, S, KR>(b, n_cu, s, ev);
+        case 4: return launch_typed<4, S, KR>(b, n_cu, s, ev);
+        case 5: return launch_typed<5, S, KR>(b, n_cu, s, ev);
+        case 6: return launch_typed<6, S, KR>(b, n_cu, s, ev);
+        case 7: return launch_typed<7, S, KR>(b, n_cu, s, ev);
+        case 8: return launch_typed<8, S, KR>(b, n_cu, s, ev);
+        default: return launch_typed<16, S, KR>(b, n_cu, s, ev);
     }
 }
 
-dvl_status launch_update(const UpdArgs& a, int n_cu, hipStream_t s, hipEvent_t* ev) {
-    if (a.dtype == DVL_F16) return launch_m<F16>(a, n_cu, s, ev);
-    if (a.dtype == DVL_BF16) return launch_m<BF16>(a, n_cu, s, ev);
-    return launch_m<F32>(a, n_cu, s, ev);
+template <typename S>
+static dvl_status launch_s(const BatchDev& b, int max_m, int max_req, int n_cu, hipStream_t s, hipEvent_t* ev) {
+    if (max_req <= 1) return launch_m<S, 1>(b, max_m, n_cu, s, ev);
+    return launch_m<S, kMaxReqPerJob>(b, max_m, n_cu, s, ev);
+}
+
+dvl_status launch_batch(const BatchDev& b, int dtype, int max_m, int max_req, int n_cu, hipStream_t s,
+                        hipEvent_t* ev) {
+    if (dtype == DVL_F16) return launch_s<F16>(b, max_m, max_req, n_cu, s, ev);
+    if (dtype == DVL_BF16) return launch_s<BF16>(b, max_m, max_req, n_cu, s, ev);
+    return launch_s<F32>(b, max_m, max_req, n_cu, s, ev);
 }
 
 }  // namespace dvl

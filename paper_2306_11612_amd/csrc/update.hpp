@@ -1,4 +1,9 @@
-// Per-update kernels (update.hip): arguments and launcher.
+// Per-update kernels (update.hip): device descriptors and launchers.
+//
+// An update batch is a list of jobs; a job is one resident volume and up to
+// kMaxReqPerJob requests (TF sets + parameters + outputs) that share one read
+// of the volume's cells in the importance pass.  A single dvl_update is a
+// batch of one job with one request.
 #pragma once
 
 #include "common.hpp"
@@ -8,10 +13,11 @@ namespace dvl {
 constexpr int kUpdThreads = 256;                 // 4 waves per workgroup
 constexpr int kCellsPerLane = 4;                 // one 4-vector per field per step
 constexpr int kStepCells = kWave * kCellsPerLane;    // 256 cells per wave step
-constexpr int kTileSteps = 16;
-constexpr int kTileCells = kStepCells * kTileSteps;  // 4096 cells per wave tile
+constexpr int kDefaultTileSteps = 16;            // 4096-cell tiles unless tuned
+constexpr int kMaxReqPerJob = 8;
+constexpr int kPhases = 5;                       // exact vmax, tile sums, carry, bin, edges
 
-// Workspace of one update, sized for n_tiles tiles and M fields.
+// Workspace of one request on a volume of T tiles and M fields.
 struct UpdWorkspace {
     double* local_prefix; // [T]  sum of the importance of earlier tiles of the same run
     double* run_total;    // [R]  sum over each run of consecutive tiles
@@ -23,49 +29,35 @@ struct UpdWorkspace {
     double* rec_sum;      // [2][M][T]
     float* rec_min;       // [2][M][T]
     float* rec_max;       // [2][M][T]
-    double* scal;         // [0] F_tot, [1] degenerate (as 0/1)
+    double* scal;         // [0] F_tot, [1] degenerate (0/1)
 };
 
 size_t workspace_bytes(int64_t n_tiles, int M);
 void workspace_carve(void* base, int64_t n_tiles, int M, UpdWorkspace* w);
 
-// Device parameter block uploaded before each update.
-struct DevParamsHeader {
-    float vmax;           // max(V) used (TF modes: host value; EXACT: device result)
-    uint32_t pad[63];     // keep the TF tables 256-byte aligned
-};
-
-struct UpdArgs {
-    int64_t n;
-    int64_t n_tiles;
-    int64_t tiles_per_run;    // K1 wave r owns tiles [r * tiles_per_run, (r + 1) * tiles_per_run)
-    int64_t n_runs;
-    int M;
-    int dtype;
-    int tf_total;         // sum of the fields' table sizes (LDS floats)
+// One request: TF tables, quantisers, parameters, workspace and outputs.
+struct ReqDev {
+    float s[kMaxFields];      // quantiser scale per field
+    float b[kMaxFields];      // quantiser offset per field
+    float nmax[kMaxFields];   // n_tf - 1 per field
+    int tf_off[kMaxFields];   // start of field m's table inside this request's block
+    const float* tf;          // this request's tables (device)
+    float* vmax_dev;          // max(V) used: host value, or computed (exact mode)
+    int tf_job_off;           // start of this request's block inside the job's tables
+    int tf_total;             // floats in this request's block
     int W;
     float exponent;
     float fmin;
     int exp_is_one;
     int clamp_mode;
-    int level_shift;      // 1: 2^L, 3: 8^L
+    int level_shift;          // 1: 2^L, 3: 8^L
     int scan_mode;
     int vmax_exact;
-    float s[kMaxFields];      // quantiser scale per field
-    float b[kMaxFields];      // quantiser offset per field
-    float nmax[kMaxFields];   // n_tf - 1 per field
-    int tf_off[kMaxFields];   // start of field m's table
-    const uint8_t* level;
-    const void* fields[kMaxFields];
-    const float* tf;      // concatenated tables, field m at tf_off[m]
-    float* vmax_dev;      // parameter block header
+    int job;
+    int pad_;
+    int64_t k3_unit0;         // first projection unit (tile) of this request
+    int64_t k4_unit0;         // first bin unit of this request
     UpdWorkspace ws;
-    // per-tile field statistics of the sorted volume (independent of the TF):
-    // sum [M][T] (fp64), min / max [M][T]
-    const double* agg_sum;
-    const float* agg_min;
-    const float* agg_max;
-    // outputs
     uint32_t* first_cell;
     uint32_t* last_cell;
     float* mean;
@@ -76,13 +68,49 @@ struct UpdArgs {
     float* vmax_used;
 };
 
-constexpr int kPhases = 5;   // exact vmax, tile sums, carry, bin, edges
+// One volume and the requests that share its reads.
+struct JobDev {
+    int64_t n;
+    int64_t n_tiles;
+    int64_t tiles_per_run;    // importance-pass wave r owns tiles [r k, (r + 1) k)
+    int64_t n_runs;
+    int64_t k1_unit0;         // first importance-pass unit (4 runs, one workgroup)
+    int M;
+    int req0;
+    int n_req;
+    int tf_total_all;         // floats of all requests' tables (LDS of the importance pass)
+    int tile_steps;           // 256-cell steps per tile
+    int pad_;
+    const uint8_t* level;
+    const void* fields[kMaxFields];
+    const double* agg_sum;    // per-tile field statistics [M][T]
+    const float* agg_min;
+    const float* agg_max;
+    const float* tf_all;      // the requests' tables, request after request
+};
 
-// ev (optional): kPhases + 1 events recorded before the first and after every phase
-dvl_status launch_update(const UpdArgs& a, int n_cu, hipStream_t s, hipEvent_t* ev = nullptr);
+struct BatchDev {
+    const JobDev* jobs;
+    const ReqDev* reqs;
+    int n_jobs;
+    int n_reqs;
+    int64_t k1_units;
+    int64_t k3_units;
+    int64_t k4_units;
+    int any_exact;
+    int max_req_tf;           // largest request table block (floats): LDS of the projection
+    int max_job_tf;           // largest job table block (floats): LDS of the importance pass
+    int pad_;
+};
 
-// Per-tile sum / min / max of one sorted field (the tiles of the update).
-dvl_status launch_tile_aggregates(int64_t n, int dtype, const void* field, int64_t n_tiles, double* sum,
-                                  float* mn, float* mx, int n_cu, hipStream_t s);
+// Launch the five phases for the batch described by `b` (descriptors already
+// resident on the device).  `max_m`, `max_req`: largest field count and
+// requests per job in the batch.  ev (optional): kPhases + 1 events.
+dvl_status launch_batch(const BatchDev& b, int dtype, int max_m, int max_req, int n_cu, hipStream_t s,
+                        hipEvent_t* ev = nullptr);
+
+// Per-tile sum / min / max of one sorted field.
+dvl_status launch_tile_aggregates(int64_t n, int dtype, const void* field, int64_t n_tiles, int tile_steps,
+                                  double* sum, float* mn, float* mx, int n_cu, hipStream_t s);
 
 }  // namespace dvl

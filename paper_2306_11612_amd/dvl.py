@@ -45,6 +45,15 @@ class dvl_bins(C.Structure):
                 ("f_total", C.c_void_p), ("vmax_used", C.c_void_p)]
 
 
+class dvl_build_options(C.Structure):
+    _fields_ = [("tile_steps", C.c_int32), ("run_waves", C.c_int32)]
+
+
+class dvl_request(C.Structure):
+    _fields_ = [("volume", C.c_void_p), ("alpha", C.c_void_p), ("n_tf", C.c_int32),
+                ("lo", C.c_void_p), ("hi", C.c_void_p), ("params", dvl_params), ("out", dvl_bins)]
+
+
 _lib = None
 
 
@@ -67,6 +76,8 @@ def lib():
     vp, i32, i64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
     sig = {
         "dvl_build_order": (i32, [i64, vp, vp, vp, vp, i32, i32, vp, vp, C.POINTER(vp)]),
+        "dvl_build_order_ex": (i32, [i64, vp, vp, vp, vp, i32, i32, vp, C.POINTER(dvl_build_options), vp,
+                                     C.POINTER(vp)]),
         "dvl_set_field": (i32, [vp, i32, vp, vp]),
         "dvl_field_range": (i32, [vp, i32, C.POINTER(f32), C.POINTER(f32)]),
         "dvl_set_tf": (i32, [vp, i32, vp, i32, f32, f32]),
@@ -83,6 +94,17 @@ def lib():
         "dvl_volume_bytes": (C.c_size_t, [vp]),
         "dvl_update_workspace_bytes": (C.c_size_t, [i64, i32, i32]),
         "dvl_destroy": (None, [vp]),
+        "dvl_executor_create": (i32, [C.POINTER(vp)]),
+        "dvl_executor_destroy": (None, [vp]),
+        "dvl_executor_bytes": (C.c_size_t, [vp]),
+        "dvl_request_bytes": (C.c_size_t, [vp, i32]),
+        "dvl_executor_set_timing": (i32, [vp, i32]),
+        "dvl_executor_kernel_times": (i32, [vp, vp, C.POINTER(i32)]),
+        "dvl_update_batch": (i32, [vp, C.POINTER(dvl_request), i32, vp]),
+        "dvl_graph_create": (i32, [C.POINTER(dvl_request), i32, C.POINTER(vp)]),
+        "dvl_graph_set_tf": (i32, [vp, i32, vp, vp, vp]),
+        "dvl_graph_launch": (i32, [vp, vp]),
+        "dvl_graph_destroy": (None, [vp]),
         "dvl_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -147,8 +169,9 @@ def params(n_bins: int, exponent: float = 1.0, min_importance: float = 0.025,
 
 # ---------------------------------------------------------------- C-ABI mirrors
 
-def build_order(x, y, z, level, fields, stream=None) -> "Volume":
-    """dvl_build_order: one-time Hilbert ordering of the cells."""
+def build_order(x, y, z, level, fields, stream=None, tile_steps: int = 0, run_waves: int = 0) -> "Volume":
+    """dvl_build_order (dvl_build_order_ex when tile_steps or run_waves is
+    given): one-time Hilbert ordering of the cells."""
     x, y, z = _dev(x, torch.int32), _dev(y, torch.int32), _dev(z, torch.int32)
     level = _dev(level, torch.uint8)
     fields = [_dev(f) for f in fields]
@@ -159,10 +182,17 @@ def build_order(x, y, z, level, fields, stream=None) -> "Volume":
         raise ValueError("fields must share one of float32 / float16 / bfloat16")
     arr = (C.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
     out = C.c_void_p()
-    st = lib().dvl_build_order(x.numel(), _ptr(x), _ptr(y), _ptr(z), _ptr(level), len(fields),
-                               _DTYPE_CODE[dt], C.cast(arr, C.c_void_p), _stream_ptr(stream),
-                               C.byref(out))
-    _check(st, "dvl_build_order")
+    if tile_steps or run_waves:
+        opt = dvl_build_options(int(tile_steps), int(run_waves))
+        st = lib().dvl_build_order_ex(x.numel(), _ptr(x), _ptr(y), _ptr(z), _ptr(level), len(fields),
+                                      _DTYPE_CODE[dt], C.cast(arr, C.c_void_p), C.byref(opt),
+                                      _stream_ptr(stream), C.byref(out))
+        _check(st, "dvl_build_order_ex")
+    else:
+        st = lib().dvl_build_order(x.numel(), _ptr(x), _ptr(y), _ptr(z), _ptr(level), len(fields),
+                                   _DTYPE_CODE[dt], C.cast(arr, C.c_void_p), _stream_ptr(stream),
+                                   C.byref(out))
+        _check(st, "dvl_build_order")
     return Volume(out)
 
 
@@ -292,3 +322,119 @@ class Volume:
 
 def update_workspace_bytes(n_cells: int, n_fields: int, n_bins: int) -> int:
     return int(lib().dvl_update_workspace_bytes(int(n_cells), int(n_fields), int(n_bins)))
+
+
+# ---------------------------------------------------------------- batches
+
+def request_bytes(vol: "Volume", n_bins: int) -> int:
+    """dvl_request_bytes: device bytes one request on `vol` needs (workspace + outputs)."""
+    return int(lib().dvl_request_bytes(vol.handle, int(n_bins)))
+
+
+class Request:
+    """One update request (``dvl_request``): a volume, its [M][n_tf] alpha
+    tables, optional windows (None: the data ranges), parameters and outputs.
+    Keeps the host arrays alive for as long as the C struct points at them."""
+
+    def __init__(self, vol: "Volume", alpha, bins: Bins | None = None, lo=None, hi=None, **kw):
+        self.vol = vol
+        a = np.ascontiguousarray(np.asarray(alpha, dtype=np.float32))
+        if a.ndim != 2 or a.shape[0] != vol.m:
+            raise ValueError(f"alpha must be [{vol.m}][n_tf], got {a.shape}")
+        self.alpha = a
+        self.lo = None if lo is None else np.ascontiguousarray(np.asarray(lo, np.float32))
+        self.hi = None if hi is None else np.ascontiguousarray(np.asarray(hi, np.float32))
+        n_bins = kw.pop("n_bins", None)
+        if bins is None:
+            bins = Bins(n_bins or 1920, vol.m)
+        self.bins = bins
+        self.params = params(bins.n_bins, **kw)
+
+    def struct(self) -> dvl_request:
+        P = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+        return dvl_request(self.vol.handle, P(self.alpha), int(self.alpha.shape[1]), P(self.lo), P(self.hi),
+                           self.params, self.bins.struct())
+
+
+def _request_array(reqs) -> C.Array:
+    arr = (dvl_request * len(reqs))()
+    for i, r in enumerate(reqs):
+        arr[i] = r.struct()
+    return arr
+
+
+class Executor:
+    """``dvl_executor``: runs batches of requests, one launch per phase."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(lib().dvl_executor_create(C.byref(h)), "dvl_executor_create")
+        self.handle = h
+
+    @property
+    def nbytes(self) -> int:
+        return int(lib().dvl_executor_bytes(self.handle))
+
+    def update_batch(self, reqs, stream=None):
+        """dvl_update_batch: enqueue every request of `reqs` on the stream."""
+        arr = _request_array(reqs)
+        _check(lib().dvl_update_batch(self.handle, arr, len(reqs), _stream_ptr(stream)), "dvl_update_batch")
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().dvl_executor_set_timing(self.handle, 1 if enable else 0), "dvl_executor_set_timing")
+
+    def kernel_times(self):
+        ms = np.zeros(5, np.float64)
+        n = C.c_int32()
+        _check(lib().dvl_executor_kernel_times(self.handle, ms.ctypes.data_as(C.c_void_p), C.byref(n)),
+               "dvl_executor_kernel_times")
+        names = ("vmax_exact", "tile_sums", "carry", "bin", "edges")
+        return dict(zip(names, ms.tolist())), int(n.value)
+
+    def close(self):
+        if self.handle:
+            lib().dvl_executor_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """``dvl_graph``: a fixed batch captured once into a HIP graph and
+    replayed with new TFs."""
+
+    def __init__(self, reqs):
+        self.reqs = list(reqs)
+        arr = _request_array(self.reqs)
+        h = C.c_void_p()
+        _check(lib().dvl_graph_create(arr, len(self.reqs), C.byref(h)), "dvl_graph_create")
+        self.handle = h
+
+    def set_tf(self, i: int, alpha, lo=None, hi=None):
+        """dvl_graph_set_tf: new [M][n_tf] tables (and windows) for request i."""
+        r = self.reqs[i]
+        a = np.ascontiguousarray(np.asarray(alpha, dtype=np.float32))
+        if a.shape != r.alpha.shape:
+            raise ValueError(f"alpha must keep the shape {r.alpha.shape}")
+        lo = None if lo is None else np.ascontiguousarray(np.asarray(lo, np.float32))
+        hi = None if hi is None else np.ascontiguousarray(np.asarray(hi, np.float32))
+        P = lambda x: None if x is None else x.ctypes.data_as(C.c_void_p)
+        _check(lib().dvl_graph_set_tf(self.handle, int(i), P(a), P(lo), P(hi)), "dvl_graph_set_tf")
+
+    def launch(self, stream=None):
+        _check(lib().dvl_graph_launch(self.handle, _stream_ptr(stream)), "dvl_graph_launch")
+
+    def close(self):
+        if self.handle:
+            lib().dvl_graph_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
