@@ -97,12 +97,114 @@ def cpu_baseline(V, alphas, n_bins: int, sample: int, exponent: float, fmin: flo
                       f"(W={n_bins}), {dt:.2f} s single-threaded fp64"}
 
 
+def bench_batch32(args, dt):
+    """32 resident volumes of 1-20 M cells (8 fields, W = 2048), every volume
+    updated after a TF change each step: as 32 sequential dvl_update calls, as
+    one dvl_update_batch, and as one captured graph (dvl_graph_launch)."""
+    import numpy as np
+    import torch
+    import synth
+    from synth.configs import config_seed
+    from paper_2306_11612_amd import dvl
+
+    W, n_vol = 2048, 32
+    t0 = time.perf_counter()
+    vols = []
+    for k in range(n_vol):
+        v = synth.cfg4_volume(k, "cuda", n_vol)
+        fields = [f.to(dt) for f in v.fields]
+        vols.append(dvl.build_order(v.x, v.y, v.z, v.level, fields))
+        del v, fields
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    gen_s = time.perf_counter() - t0
+    cells = sum(V.n for V in vols)
+    M = vols[0].m
+    log(f"{n_vol} volumes, {cells} cells, resident in {gen_s:.1f} s")
+    tfs = [[np.stack([t.numpy() for t in synth.make_tfs(config_seed(4) * 1000 + k + 101 * s, M, (4, 4))])
+            for s in range(2)] for k in range(n_vol)]
+    kw = dict(exponent=args.exponent, min_importance=args.min_importance)
+
+    def timed(step, label):
+        for k in range(args.warmup):
+            step(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(k)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        log(f"{label}: {ms:.3f} ms per step of {n_vol} updates")
+        return ms
+
+    bins = [dvl.Bins(W, M) for _ in vols]
+
+    def seq(k):
+        for i, V in enumerate(vols):
+            A = tfs[i][k & 1]
+            for m in range(M):
+                V.set_tf(m, A[m])
+            V.update(bins[i], **kw)
+    ms_seq = timed(seq, "sequential dvl_update")
+
+    ex = dvl.Executor()
+    reqs = [dvl.Request(V, tfs[i][0], bins[i], **kw) for i, V in enumerate(vols)]
+
+    def batch(k):
+        for i, r in enumerate(reqs):
+            r.alpha = np.ascontiguousarray(tfs[i][k & 1])
+        ex.update_batch(reqs)
+    ms_batch = timed(batch, "dvl_update_batch")
+    ex.set_timing(True)
+    ex.kernel_times()
+    for k in range(args.steps):
+        batch(k)
+    phases, nb = ex.kernel_times()
+    ex.set_timing(False)
+    per_launch = {k: v / max(nb, 1) for k, v in phases.items()}
+
+    g = dvl.Graph(reqs)
+
+    def graph(k):
+        for i in range(n_vol):
+            g.set_tf(i, tfs[i][k & 1])
+        g.launch()
+    ms_graph = timed(graph, "captured graph")
+    cached = all(V.entry_cache_info() is not None for V in vols)
+    elem = 4 if args.dtype == "f32" else 2
+    bpc = (M + 1) if cached else (M * elem + 1)
+    achieved = cells * bpc / (per_launch["tile_sums"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": cells / (ms_graph * 1e-3), "unit": "cells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "batch32: 32 AMR volumes of 1-20 M cells (log-uniform), 2-4 levels, 8 fields, "
+                               "one TF change per volume per step", "n_volumes": n_vol, "n_cells": cells,
+                   "n_fields": M, "n_bins": W, "exponent": args.exponent, "min_importance": args.min_importance},
+        "roofline": {"bound": "hbm", "kernel": "tile_sums" + ("[entries]" if cached else ""),
+                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "bytes_per_launch": cells * bpc,
+                     "bytes_per_cell": bpc, "avg_launch_ms": per_launch["tile_sums"]},
+        "entry_cache": cached,
+        "sequential_ms_per_step": ms_seq, "batch_ms_per_step": ms_batch, "graph_ms_per_step": ms_graph,
+        "speedup_graph_vs_sequential": ms_seq / ms_graph,
+        "kernel_ms_per_batch": per_launch, "generation_s": gen_s,
+    }
+    g.close()
+    ex.close()
+    for V in vols:
+        V.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="amr5_500m", choices=["amr5_500m", "amr3_12m", "grid64"])
+    ap.add_argument("--workload", default="amr5_500m", choices=["amr5_500m", "amr3_12m", "grid64", "batch32"])
+    ap.add_argument("--entry-cache", default="auto", choices=["auto", "never"],
+                    help="TF entry cache policy of the timed updates (auto: the library default)")
     ap.add_argument("--base", type=int, default=None, help="override the base grid side")
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--bins", type=int, default=1920)
@@ -141,6 +243,8 @@ def main():
 
     import synth.amr
     synth.amr.PROGRESS = log
+    if args.workload == "batch32":
+        return bench_batch32(args, dt)
     t0 = time.perf_counter()
     vol, seed, desc = make_workload(args.workload, args.base, "cuda")
     torch.cuda.synchronize()
@@ -174,37 +278,51 @@ def main():
             dvl.set_tf(V, m, A[m], lo, hi)
         V.update(bins, **kw)
 
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    log("warmup done")
+    def measure(policy):
+        V.set_entry_cache(policy)
+        for k in range(args.warmup):
+            step(k)
+        torch.cuda.synchronize()
+        V.set_timing(True)
+        V.kernel_times()   # reset
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(k)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phases, n_upd = V.kernel_times()
+        V.set_timing(False)
+        ms = wall * 1e3 / args.steps
+        cached = V.entry_cache_info() is not None
+        log(f"entry cache {'on' if cached else 'off'}: {args.steps} steps in {wall:.3f} s: {ms:.3f} ms/update; "
+            f"kernels {phases}")
+        return ms, {k: v / max(n_upd, 1) for k, v in phases.items()}, cached
 
-    V.set_timing(True)
-    V.kernel_times()   # reset
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(k)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    phases, n_upd = V.kernel_times()
-    V.set_timing(False)
-    ms_per_step = wall * 1e3 / args.steps
-    log(f"{args.steps} steps in {wall:.3f} s: {ms_per_step:.3f} ms/update; kernels {phases}")
+    # The value path first (every update reads the fields), then the library
+    # default: from the second update with unchanged windows on, the importance
+    # pass reads the cached TF entries (one byte per cell and field).
+    elem = 4 if args.dtype == "f32" else 2
+    value_bpc = M * elem + 1
+    ms_values, per_launch_values, _ = measure(dvl.ENTRY_CACHE_NEVER)
+    if args.entry_cache == "never":
+        ms_per_step, per_launch, cached = ms_values, per_launch_values, False
+    else:
+        ms_per_step, per_launch, cached = measure(dvl.ENTRY_CACHE_AUTO)
 
     # roofline of the dominant kernel (the importance pass): it streams every
-    # cell's level and M fields once.  The projection pass re-reads only tiles
-    # that contain a bin edge (at most min(tiles, W) of them).
-    elem = 4 if args.dtype == "f32" else 2
-    bytes_per_cell = M * elem + 1
+    # cell's level and its M field values (or M cached entries) once.  The
+    # projection pass re-reads the values of the tiles that contain a bin
+    # edge only (at most min(tiles, W) of them).
+    bytes_per_cell = (M + 1) if cached else value_bpc
     alg_bytes = n * bytes_per_cell
-    per_launch = {k: v / max(n_upd, 1) for k, v in phases.items()}
     dom = max(("tile_sums", "bin"), key=lambda k: per_launch[k])
     achieved = alg_bytes / (per_launch[dom] * 1e-3) / 1e9
     n_tiles = (n + 4095) // 4096
-    rescan_bytes = min(n_tiles, args.bins) * 4096 * bytes_per_cell
+    rescan_bytes = min(n_tiles, args.bins) * 4096 * value_bpc
     update_bytes = alg_bytes + rescan_bytes
     update_gbps = update_bytes / (ms_per_step * 1e-3) / 1e9
+    values_gbps = n * value_bpc / (per_launch_values["tile_sums"] * 1e-3) / 1e9
 
     out = {
         "metric": METRIC,
@@ -222,11 +340,18 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "n_cells": n, "n_fields": M,
                    "field_storage": args.dtype, "n_bins": args.bins, "exponent": args.exponent,
                    "min_importance": args.min_importance, "tf_control_points": 4},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+        "roofline": {"bound": "hbm", "kernel": dom + ("[entries]" if cached and dom == "tile_sums" else ""),
+                     "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": profiled_traffic(args.workload, args.dtype, dom),
+                     "traffic": profiled_traffic(args.workload, args.dtype, dom + ("_entries" if cached else "")),
                      "bytes_per_launch": alg_bytes, "bytes_per_cell": bytes_per_cell,
                      "avg_launch_ms": per_launch[dom]},
+        "entry_cache": cached,
+        "no_entry_cache": {"ms_per_step": ms_values, "value": n / (ms_values * 1e-3),
+                           "tile_sums_ms": per_launch_values["tile_sums"], "tile_sums_gbps": values_gbps,
+                           "tile_sums_frac": values_gbps / HBM_PEAK_GBPS, "bytes_per_cell": value_bpc,
+                           "traffic": profiled_traffic(args.workload, args.dtype, "tile_sums"),
+                           "kernel_ms_per_update": per_launch_values},
         "update_bytes": update_bytes,
         "update_hbm_gbps": update_gbps,
         "update_hbm_frac": update_gbps / HBM_PEAK_GBPS,

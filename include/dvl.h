@@ -102,11 +102,33 @@ dvl_status dvl_build_order(int64_t n_cells, const int32_t* x, const int32_t* y,
  *                projection reads again only tiles that contain a bin edge.
  *   run_waves    the importance pass splits the tiles into at most this many
  *                runs of consecutive tiles, one wave each (0: 32 per compute
- *                unit); 64 <= run_waves <= 65536 otherwise. */
+ *                unit); 64 <= run_waves <= 65536 otherwise.
+ *   entry_cache  the TF entry of a cell (Eq. 1's lookup) depends on its value
+ *                and the field's window and table size only, not on the
+ *                alpha values.  With tables of at most 256 entries the volume
+ *                may keep one byte per cell and field holding it, so that the
+ *                importance pass reads M + 1 bytes per cell instead of the
+ *                values; results are bitwise the same.  The cache is built
+ *                for one set of windows and table sizes:
+ *                DVL_ENTRY_CACHE_AUTO (0) when two consecutive updates use
+ *                the same set, DVL_ENTRY_CACHE_ALWAYS on the first use of a
+ *                set, DVL_ENTRY_CACHE_NEVER never.  A (re)build costs one
+ *                pass over the fields, synchronises the device before and
+ *                the stream after it, and takes n_cells bytes per field. */
+enum { DVL_ENTRY_CACHE_AUTO = 0, DVL_ENTRY_CACHE_ALWAYS = 1, DVL_ENTRY_CACHE_NEVER = 2 };
 typedef struct {
     int32_t tile_steps;
     int32_t run_waves;
+    int32_t entry_cache;
 } dvl_build_options;
+
+/* Change the entry-cache policy of a volume (DVL_ENTRY_CACHE_*).  NEVER also
+ * frees the cache (after synchronising the device).  Host only. */
+dvl_status dvl_set_entry_cache(dvl_volume* v, int32_t policy);
+/* 1 if the volume holds a built TF entry cache, with the windows and table
+ * sizes it was built for in lo/hi/n_tf (host [n_fields] each, any may be
+ * NULL); 0 if not. */
+int32_t dvl_entry_cache_info(const dvl_volume* v, float* lo, float* hi, int32_t* n_tf);
 
 /* dvl_build_order with explicit options (NULL: defaults). */
 dvl_status dvl_build_order_ex(int64_t n_cells, const int32_t* x, const int32_t* y,

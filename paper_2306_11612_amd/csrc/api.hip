@@ -74,6 +74,19 @@ static float unkey(unsigned int u) {
 constexpr int kRing = 4;                 // descriptor uploads that may be in flight
 constexpr int kJobTfFloats = 32768;      // LDS budget of one job's tables (128 KB)
 
+// The quantisers of every field: the TF entry of a cell depends on its value
+// and on these only, not on the alpha tables.
+struct CacheKey {
+    int M = 0;
+    int n_tf[kMaxFields] = {};
+    float s[kMaxFields] = {}, b[kMaxFields] = {};
+    float lo[kMaxFields] = {}, hi[kMaxFields] = {};   // the windows (informational, not compared)
+    bool operator==(const CacheKey& o) const {
+        return M == o.M && memcmp(n_tf, o.n_tf, sizeof n_tf) == 0 && memcmp(s, o.s, sizeof s) == 0 &&
+               memcmp(b, o.b, sizeof b) == 0;
+    }
+};
+
 struct Executor;
 
 }  // namespace dvl
@@ -103,6 +116,15 @@ struct dvl_volume {
     double* agg_sum = nullptr;
     float* agg_min = nullptr;
     float* agg_max = nullptr;
+    // TF entry cache: one byte per sorted cell and field for one CacheKey
+    // (policy DVL_ENTRY_CACHE_*); `cand` is the key of the last update that
+    // could have used a cache, so a key seen twice in a row gets one
+    uint8_t* idx_s[kMaxFields] = {};
+    int32_t idx_policy = DVL_ENTRY_CACHE_AUTO;
+    bool idx_valid = false;
+    CacheKey idx_key;
+    bool cand_set = false;
+    CacheKey cand_key;
     // the volume's own transfer functions (used by dvl_update)
     bool tf_set[kMaxFields] = {};
     std::vector<float> alpha[kMaxFields];
@@ -308,8 +330,11 @@ struct Plan {
     int any_exact = 0;
     int64_t k1_units = 0, k3_units = 0, k4_units = 0;
     size_t tf_floats = 0;
-    // descriptor block: [JobDev x jobs][ReqDev x reqs][max V x reqs][tables]
+    // descriptor block, uploaded before every launch:
+    //   [header: rescan counter][JobDev x jobs][ReqDev x reqs][max V x reqs][tables]
+    // followed on the device (not uploaded) by the rescan queue [k3_units]
     size_t off_jobs = 0, off_reqs = 0, off_vmax = 0, off_tf = 0, block_bytes = 0;
+    size_t off_queue = 0, device_bytes = 0;
 };
 
 // Group the requests into jobs (one volume; at most kMaxReqPerJob requests
@@ -413,11 +438,13 @@ static dvl_status plan_batch(std::vector<ReqHost>&& reqs, Plan& P) {
         d.f_total = r.out.f_total;
         d.vmax_used = r.out.vmax_used;
     }
-    P.off_jobs = 0;
-    P.off_reqs = al256(P.jobs.size() * sizeof(JobDev));
+    P.off_jobs = 256;
+    P.off_reqs = P.off_jobs + al256(P.jobs.size() * sizeof(JobDev));
     P.off_vmax = P.off_reqs + al256(P.rdev.size() * sizeof(ReqDev));
     P.off_tf = P.off_vmax + al256(P.rdev.size() * sizeof(float));
     P.block_bytes = P.off_tf + al256(P.tf_floats * sizeof(float));
+    P.off_queue = P.block_bytes;
+    P.device_bytes = P.off_queue + al256((size_t)P.k3_units * sizeof(uint64_t));
     return DVL_OK;
 }
 
@@ -441,15 +468,110 @@ static dvl_status fill_block(Plan& P, char* h, char* d) {
         P.rdev[q].vmax_dev = (float*)(d + P.off_vmax) + q;
     }
     for (auto& j : P.jobs) j.tf_all = (const float*)(d + P.off_tf) + P.reqs[j.req0].tf_pos;
+    memset(h, 0, P.off_jobs);   // rescan counter starts at 0
     memcpy(h + P.off_jobs, P.jobs.data(), P.jobs.size() * sizeof(JobDev));
     memcpy(h + P.off_reqs, P.rdev.data(), P.rdev.size() * sizeof(ReqDev));
     return DVL_OK;
 }
 
-static BatchDev batch_dev(const Plan& P, char* d) {
+// The entry-cache key of a request, if its tables fit in a byte index.
+static bool key_of(const ReqHost& r, CacheKey& k) {
+    k = CacheKey();
+    k.M = r.v->M;
+    for (int m = 0; m < r.v->M; ++m) {
+        if (r.n_tf[m] > 256) return false;
+        k.n_tf[m] = r.n_tf[m];
+        k.s[m] = r.qs[m];
+        k.b[m] = r.qb[m];
+        k.lo[m] = r.lo[m];
+        k.hi[m] = r.hi[m];
+    }
+    return true;
+}
+
+struct CacheBuild {
+    dvl_volume* v;
+    CacheKey key;
+};
+
+// Choose, per job, between reading the field values and reading the
+// volume's TF entry cache; schedule the cache (re)builds this launch needs.
+// A job reads the cache if all its requests share one key and the cache holds
+// it (or is built for it now).  One volume's cache serves one key per launch.
+static dvl_status decide_cache(Plan& P, std::vector<CacheBuild>& builds) {
+    builds.clear();
+    std::vector<std::pair<dvl_volume*, CacheKey>> serving;   // cache contents per volume in this launch
+    for (JobDev& j : P.jobs) {
+        for (int m = 0; m < kMaxFields; ++m) j.idx[m] = nullptr;
+        dvl_volume* v = P.reqs[j.req0].v;
+        if (v->idx_policy == DVL_ENTRY_CACHE_NEVER) continue;
+        CacheKey key;
+        bool agree = key_of(P.reqs[j.req0], key);
+        for (int k = 1; agree && k < j.n_req; ++k) {
+            CacheKey k2;
+            agree = key_of(P.reqs[j.req0 + k], k2) && k2 == key;
+        }
+        if (!agree) continue;
+        auto it = std::find_if(serving.begin(), serving.end(), [&](const auto& e) { return e.first == v; });
+        bool use = false;
+        if (it != serving.end()) {
+            use = it->second == key;            // another key already serves this launch: values
+        } else if (v->idx_valid && v->idx_key == key) {
+            use = true;
+        } else if (v->idx_policy == DVL_ENTRY_CACHE_ALWAYS || (v->cand_set && v->cand_key == key)) {
+            for (int m = 0; m < v->M; ++m) {
+                if (v->idx_s[m]) continue;
+                DevBuf b;
+                if (dvl_status st = b.alloc((size_t)v->n_pad, "TF entry cache")) return st;
+                v->idx_s[m] = (uint8_t*)b.release();
+                v->bytes += (size_t)v->n_pad;
+            }
+            builds.push_back({v, key});
+            use = true;
+        } else {
+            v->cand_key = key;
+            v->cand_set = true;
+        }
+        if (use) {
+            if (it == serving.end()) serving.push_back({v, key});
+            for (int m = 0; m < v->M; ++m) j.idx[m] = v->idx_s[m];
+        }
+    }
+    return DVL_OK;
+}
+
+// Rebuild the scheduled caches on stream s.  Work on other streams may still
+// read a cache, and later launches on other streams must see the new one, so
+// a rebuild waits for the device before and for the stream after.
+static dvl_status run_cache_builds(const std::vector<CacheBuild>& builds, hipStream_t s) {
+    if (builds.empty()) return DVL_OK;
+    DVL_HIP(hipDeviceSynchronize());
+    for (const CacheBuild& cb : builds) {
+        dvl_volume* v = cb.v;
+        v->idx_valid = false;
+        for (int m = 0; m < v->M; ++m)
+            if (dvl_status st = launch_build_index(v->n_pad, v->dtype, v->fields_s[m], cb.key.s[m], cb.key.b[m],
+                                                   cb.key.n_tf[m], v->idx_s[m], v->n_cu, s))
+                return st;
+    }
+    DVL_HIP(hipStreamSynchronize(s));
+    for (const CacheBuild& cb : builds) {
+        cb.v->idx_key = cb.key;
+        cb.v->idx_valid = true;
+        cb.v->cand_set = false;
+    }
+    return DVL_OK;
+}
+
+// `paths`: importance-pass variants to launch (a captured graph takes both,
+// since its jobs choose at every launch)
+static BatchDev batch_dev(const Plan& P, char* d, int paths) {
     BatchDev b{};
+    b.paths = paths;
     b.jobs = (const JobDev*)(d + P.off_jobs);
     b.reqs = (const ReqDev*)(d + P.off_reqs);
+    b.rescan_count = (uint32_t*)d;
+    b.rescan_queue = (uint64_t*)(d + P.off_queue);
     b.n_jobs = (int)P.jobs.size();
     b.n_reqs = (int)P.rdev.size();
     b.k1_units = P.k1_units;
@@ -522,6 +644,7 @@ struct Executor {
     }
 
     // the next ring slot, its previous upload complete, large enough for `need`
+    // bytes on the device (the uploaded block is a prefix of them)
     dvl_status take_slot(size_t need, Slot** out) {
         Slot& s = ring[next];
         next = (next + 1) % kRing;
@@ -576,15 +699,20 @@ struct Executor {
             if (dvl_status st = ensure_ws(q, request_ws_bytes(P.reqs[q].v))) return st;
             workspace_carve(ws[q].first, P.reqs[q].v->n_tiles, P.reqs[q].v->M, &P.rdev[q].ws);
         }
+        std::vector<CacheBuild> builds;
+        if (dvl_status st = decide_cache(P, builds)) return st;
+        if (dvl_status st = run_cache_builds(builds, s)) return st;
         Slot* slot = nullptr;
-        if (dvl_status st = take_slot(P.block_bytes, &slot)) return st;
+        if (dvl_status st = take_slot(P.device_bytes, &slot)) return st;
         if (dvl_status st = fill_block(P, slot->host, slot->dev)) return st;
         DVL_HIP(hipMemcpyAsync(slot->dev, slot->host, P.block_bytes, hipMemcpyHostToDevice, s));
         DVL_HIP(hipEventRecord(slot->ev, s));
         slot->used = true;
         hipEvent_t* ev = nullptr;
         if (dvl_status st = timing_events(&ev)) return st;
-        return launch_batch(batch_dev(P, slot->dev), P.dtype, P.max_m, P.max_req, n_cu, s, ev);
+        int paths = 0;
+        for (const JobDev& j : P.jobs) paths |= j.idx[0] ? kPathEntries : kPathValues;
+        return launch_batch(batch_dev(P, slot->dev, paths), P.dtype, P.max_m, P.max_req, n_cu, s, ev);
     }
 
     dvl_status kernel_times(double* ms, int32_t* n) {
@@ -690,8 +818,11 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
     if (!x || !y || !z || !level || !fields) return fail(DVL_E_INVALID, "NULL input pointer");
     for (int m = 0; m < M; ++m)
         if (!fields[m]) return fail(DVL_E_INVALID, "field %d pointer is NULL", m);
-    int tile_steps = kDefaultTileSteps, run_waves = 0;
+    int tile_steps = kDefaultTileSteps, run_waves = 0, entry_cache = DVL_ENTRY_CACHE_AUTO;
     if (opt) {
+        if (opt->entry_cache < DVL_ENTRY_CACHE_AUTO || opt->entry_cache > DVL_ENTRY_CACHE_NEVER)
+            return fail(DVL_E_INVALID, "entry_cache %d", opt->entry_cache);
+        entry_cache = opt->entry_cache;
         if (opt->tile_steps != 0 && opt->tile_steps != 8 && opt->tile_steps != 16 && opt->tile_steps != 32)
             return fail(DVL_E_INVALID, "tile_steps %d (0, 8, 16 or 32)", opt->tile_steps);
         if (opt->run_waves != 0 && (opt->run_waves < 64 || opt->run_waves > 65536))
@@ -709,6 +840,7 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
     v->M = M;
     v->dtype = dtype;
     v->tile_steps = tile_steps;
+    v->idx_policy = entry_cache;
     const int64_t tile_cells = (int64_t)tile_steps * kStepCells;
     v->n_tiles = (n + tile_cells - 1) / tile_cells;
     v->n_pad = v->n_tiles * tile_cells;
@@ -829,6 +961,8 @@ dvl_status dvl_set_field(dvl_volume* v, int32_t m, const void* values, void* str
     if (!values) return fail(DVL_E_INVALID, "values is NULL");
     hipStream_t s = (hipStream_t)stream;
     const int eb = elem_bytes_of(v->dtype);
+    v->idx_valid = false;      // the cached entries describe the old values
+    v->cand_set = false;
     DevBuf rng;
     if (dvl_status st = rng.alloc(4 * sizeof(unsigned int), "range")) return st;
     unsigned int r[4] = {0xFFFFFFFFu, 0u, 0u, 0u};
@@ -958,6 +1092,36 @@ dvl_status dvl_kernel_times(dvl_volume* v, double* ms, int32_t* n_updates) {
     return v->ex->kernel_times(ms, n_updates);
 }
 
+dvl_status dvl_set_entry_cache(dvl_volume* v, int32_t policy) {
+    g_err.clear();
+    if (dvl_status st = check_volume(v)) return st;
+    if (policy < DVL_ENTRY_CACHE_AUTO || policy > DVL_ENTRY_CACHE_NEVER)
+        return fail(DVL_E_INVALID, "entry_cache %d", policy);
+    v->idx_policy = policy;
+    if (policy == DVL_ENTRY_CACHE_NEVER) {
+        DVL_HIP(hipDeviceSynchronize());   // queued updates may still read it
+        for (int m = 0; m < kMaxFields; ++m) {
+            if (!v->idx_s[m]) continue;
+            (void)hipFree(v->idx_s[m]);
+            v->idx_s[m] = nullptr;
+            v->bytes -= (size_t)v->n_pad;
+        }
+        v->idx_valid = false;
+        v->cand_set = false;
+    }
+    return DVL_OK;
+}
+
+int32_t dvl_entry_cache_info(const dvl_volume* v, float* lo, float* hi, int32_t* n_tf) {
+    if (!v || !v->idx_valid) return 0;
+    for (int m = 0; m < v->M; ++m) {
+        if (lo) lo[m] = v->idx_key.lo[m];
+        if (hi) hi[m] = v->idx_key.hi[m];
+        if (n_tf) n_tf[m] = v->idx_key.n_tf[m];
+    }
+    return 1;
+}
+
 int64_t dvl_num_cells(const dvl_volume* v) { return v ? v->n : 0; }
 int32_t dvl_num_fields(const dvl_volume* v) { return v ? v->M : 0; }
 int32_t dvl_grid_bits(const dvl_volume* v) { return v ? v->bits : 0; }
@@ -976,6 +1140,8 @@ void dvl_destroy(dvl_volume* v) {
     if (v->agg_sum) (void)hipFree(v->agg_sum);
     if (v->agg_min) (void)hipFree(v->agg_min);
     if (v->agg_max) (void)hipFree(v->agg_max);
+    for (int m = 0; m < kMaxFields; ++m)
+        if (v->idx_s[m]) (void)hipFree(v->idx_s[m]);
     delete v;
 }
 
@@ -1041,7 +1207,7 @@ dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph**
         workspace_carve(g->ws.back(), P.reqs[q].v->n_tiles, P.reqs[q].v->M, &P.rdev[q].ws);
     }
     DevBuf d;
-    if (dvl_status st = d.alloc(P.block_bytes, "graph descriptors")) return st;
+    if (dvl_status st = d.alloc(P.device_bytes, "graph descriptors")) return st;
     g->dev = (char*)d.release();
     {
         // a first descriptor image validates the tables (range checks) before anything is captured
@@ -1063,7 +1229,8 @@ dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph**
         (void)hipStreamDestroy(cs);
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    const dvl_status cst = launch_batch(batch_dev(P, g->dev), P.dtype, P.max_m, P.max_req, g->n_cu, cs, nullptr);
+    const dvl_status cst = launch_batch(batch_dev(P, g->dev, kPathValues | kPathEntries), P.dtype, P.max_m,
+                                        P.max_req, g->n_cu, cs, nullptr);
     const hipError_t ee = hipStreamEndCapture(cs, &g->graph);
     (void)hipStreamDestroy(cs);
     if (cst != DVL_OK) return cst;
@@ -1099,6 +1266,9 @@ dvl_status dvl_graph_launch(dvl_graph* g, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const int r = g->next;
     if (g->used[r]) DVL_HIP(hipEventSynchronize(g->ev[r]));
+    std::vector<CacheBuild> builds;
+    if (dvl_status st = decide_cache(g->plan, builds)) return st;
+    if (dvl_status st = run_cache_builds(builds, s)) return st;
     if (dvl_status st = fill_block(g->plan, g->host[r], g->dev)) return st;
     g->next = (r + 1) % kRing;
     DVL_HIP(hipMemcpyAsync(g->dev, g->host[r], g->plan.block_bytes, hipMemcpyHostToDevice, s));

@@ -9,9 +9,10 @@
 //                     consecutive tiles and records their prefix inside it
 //   K2 k_carry        per request: exclusive scan of the run totals (Eq. 4
 //                     across runs; fp64 or compensated fp32), made monotone
-//   K3 k_bin          per (request, tile): if the tile's pixel interval lies
-//                     inside one bin, its precomputed field statistics are its
-//                     record; otherwise recompute f, monotone in-tile prefix,
+//   K3a k_classify    per (request, tile), one lane each: if the tile's pixel
+//                     interval lies inside one bin, its precomputed field
+//                     statistics are its record; otherwise the tile is queued
+//   K3b k_bin         per queued tile: recompute f, monotone in-tile prefix,
 //                     pixel interval of every cell; bins complete inside the
 //                     tile are finalised directly, its first and last bin go
 //                     to per-tile partial records
@@ -140,6 +141,23 @@ __device__ __forceinline__ float variation(const float (&x)[MT], int M, const fl
     return amax - amin;
 }
 
+// Eq. 1 from cached TF entries: byte k of packed[m] is the entry of cell k
+template <int MT>
+__device__ __forceinline__ float variation_idx(const uint32_t (&packed)[MT], int k, int M,
+                                               const float* __restrict__ tf, const ReqDev& q) {
+    float amax = -INFINITY, amin = INFINITY;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        if (m < M) {
+            const int e = (int)((packed[m] >> (8 * k)) & 0xFFu);
+            const float al = tf[q.tf_off[m] + e];
+            amax = fmaxf(amax, al);
+            amin = fminf(amin, al);
+        }
+    }
+    return amax - amin;
+}
+
 // Eq. 3 with the minimum importance
 __device__ __forceinline__ float importance_from_v(float v, uint32_t L, const ImpCtx& c) {
     const float r = v * c.inv_vmax;
@@ -176,60 +194,109 @@ struct StepData {
     }
 };
 
+// TF entries of the 4 cells of this lane in the given step, from the
+// volume's entry cache (one byte per cell and field)
+template <int MT>
+struct StepIdx {
+    uint32_t e[MT];
+    uint32_t lv;
+    __device__ __forceinline__ void load(const JobDev& j, int M, int64_t quad) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            if (m < M) e[m] = reinterpret_cast<const uint32_t*>(j.idx[m])[quad];
+        lv = reinterpret_cast<const uint32_t*>(j.level)[quad];
+    }
+};
+
+// V of cell k of this lane for request q, from values or from cached entries
+template <int MT, typename S>
+__device__ __forceinline__ float cell_v(const StepData<MT, S>& d, int k, int M, const float* tf, const ReqDev& q) {
+    float xk[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) xk[m] = m < M ? d.q[m].get(k) : 0.0f;
+    return variation<MT>(xk, M, tf, q);
+}
+template <int MT>
+__device__ __forceinline__ float cell_v(const StepIdx<MT>& d, int k, int M, const float* tf, const ReqDev& q) {
+    return variation_idx<MT>(d.e, k, M, tf, q);
+}
+
+// How many steps one loop iteration loads ahead: one 4-vector per field is
+// enough to keep HBM busy; cached entries are a quarter of that, so four
+// steps go together (tiles hold a multiple of four steps and are padded, so
+// the loads of a group stay inside the volume's buffers).
+template <typename D> struct Group { static constexpr int n = 1; };
+template <int MT> struct Group<StepIdx<MT>> { static constexpr int n = 4; };
+
 // ------------------------------------------------------------------ K0
 
-template <int MT, typename S, int KR>
+template <int MT, int KR, typename D>
+__device__ void vmax_run(const BatchDev& b, const JobDev& j, int64_t r, const float* tf_lds) {
+    constexpr int G = Group<D>::n;
+    const int lane = lane_id();
+    const int M = fields_of<MT>(j.M);
+    const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
+    const int64_t c_begin = r * j.tiles_per_run * tile_cells;
+    const int64_t c_end = min(j.n, (r + 1) * j.tiles_per_run * tile_cells);
+    const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
+    const ReqDev* rq = b.reqs + j.req0;
+    float vmax[KR];
+#pragma unroll
+    for (int q = 0; q < KR; ++q) vmax[q] = 0.0f;
+    for (int s = 0; s < nsteps; s += G) {
+        D d[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) d[g].load(j, M, ((c_begin + (int64_t)(s + g) * kStepCells) >> 2) + lane);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (s + g >= nsteps) break;
+            const int64_t quad = ((c_begin + (int64_t)(s + g) * kStepCells) >> 2) + lane;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((quad << 2) + k >= j.n) continue;
+#pragma unroll
+                for (int q = 0; q < KR; ++q)
+                    if (q < j.n_req && rq[q].vmax_exact)
+                        vmax[q] = fmaxf(vmax[q], cell_v<MT>(d[g], k, M, tf_lds + rq[q].tf_job_off, rq[q]));
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < KR; ++q) {
+        if (q < j.n_req && rq[q].vmax_exact) {
+            const float v = wave_max_f(vmax[q]);
+            if (lane == 0 && v > 0.0f) atomicMax(reinterpret_cast<unsigned int*>(rq[q].vmax_dev), __float_as_uint(v));
+        }
+    }
+}
+
+// the job's TF tables into LDS when the workgroup moves to another job
+__device__ __forceinline__ void load_job_tables(const JobDev& j, int ji, int& loaded, float* tf_lds) {
+    if (ji != loaded) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < j.tf_total_all; i += blockDim.x) tf_lds[i] = j.tf_all[i];
+        __syncthreads();
+        loaded = ji;
+    }
+}
+
+// IDX: this instance serves the jobs that read cached entries (1) or values (0)
+template <int MT, typename S, int KR, int IDX>
 __global__ __launch_bounds__(kUpdThreads) void k_vmax_exact(BatchDev b) {
     extern __shared__ float tf_lds[];
-    const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
     int loaded = -1;
     for (int64_t u = blockIdx.x; u < b.k1_units; u += gridDim.x) {
         const int ji = find_job_k1(b, u);
         const JobDev& j = b.jobs[ji];
-        if (ji != loaded) {
-            __syncthreads();
-            for (int i = threadIdx.x; i < j.tf_total_all; i += blockDim.x) tf_lds[i] = j.tf_all[i];
-            __syncthreads();
-            loaded = ji;
-        }
-        const int M = fields_of<MT>(j.M);
+        if ((j.idx[0] != nullptr) != (IDX != 0)) continue;
+        load_job_tables(j, ji, loaded, tf_lds);
         const int64_t r = (u - j.k1_unit0) * (kUpdThreads / kWave) + wv;
         if (r >= j.n_runs) continue;
-        const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
-        const int64_t c_begin = r * j.tiles_per_run * tile_cells;
-        const int64_t c_end = min(j.n, (r + 1) * j.tiles_per_run * tile_cells);
-        const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
-        float vmax[KR];
-#pragma unroll
-        for (int q = 0; q < KR; ++q) vmax[q] = 0.0f;
-        for (int s = 0; s < nsteps; ++s) {
-            const int64_t quad = ((c_begin + (int64_t)s * kStepCells) >> 2) + lane;
-            StepData<MT, S> d;
-            d.load(j, M, quad);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                float x[MT];
-#pragma unroll
-                for (int m = 0; m < MT; ++m) x[m] = m < M ? d.q[m].get(k) : 0.0f;
-                if ((quad << 2) + k >= j.n) continue;
-#pragma unroll
-                for (int q = 0; q < KR; ++q) {
-                    if (q < j.n_req && b.reqs[j.req0 + q].vmax_exact) {
-                        const ReqDev& rq = b.reqs[j.req0 + q];
-                        vmax[q] = fmaxf(vmax[q], variation<MT>(x, M, tf_lds + rq.tf_job_off, rq));
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < KR; ++q) {
-            if (q < j.n_req && b.reqs[j.req0 + q].vmax_exact) {
-                const float v = wave_max_f(vmax[q]);
-                if (lane == 0 && v > 0.0f)
-                    atomicMax(reinterpret_cast<unsigned int*>(b.reqs[j.req0 + q].vmax_dev), __float_as_uint(v));
-            }
-        }
+        if constexpr (IDX != 0)
+            vmax_run<MT, KR, StepIdx<MT>>(b, j, r, tf_lds);
+        else
+            vmax_run<MT, KR, StepData<MT, S>>(b, j, r, tf_lds);
     }
 }
 
@@ -259,77 +326,64 @@ struct RunAcc {
     }
 };
 
-// A workgroup takes 4 consecutive runs of one job; wave r of the job owns the
-// tiles [r k, (r + 1) k).  It streams their cells once, evaluates f for every
-// request of the job, sums f over each tile in fp64 and records, per request
-// and tile, the (non-decreasing) sum of the earlier tiles of its run.
-template <int MT, typename S, int KR>
-__global__ __launch_bounds__(kUpdThreads) void k_tile_sums(BatchDev b) {
-    extern __shared__ float tf_lds[];
+// One wave's run r of job j: stream its cells once (values, or cached
+// entries), evaluate f for every request of the job, sum f over each tile in
+// fp64 (per lane, 4 cells per step as (f0 + f1) + (f2 + f3), then the wave)
+// and record, per request and tile, the non-decreasing sum of the earlier
+// tiles of the run.  Both sources give the same f bit for bit.
+template <int MT, int KR, typename D>
+__device__ void tile_sums_run(const BatchDev& b, const JobDev& j, int64_t r, const float* tf_lds) {
+    constexpr int G = Group<D>::n;
     const int lane = lane_id();
-    const int wv = threadIdx.x / kWave;
-    int loaded = -1;
-    for (int64_t u = blockIdx.x; u < b.k1_units; u += gridDim.x) {
-        const int ji = find_job_k1(b, u);
-        const JobDev& j = b.jobs[ji];
-        if (ji != loaded) {
-            __syncthreads();
-            for (int i = threadIdx.x; i < j.tf_total_all; i += blockDim.x) tf_lds[i] = j.tf_all[i];
-            __syncthreads();
-            loaded = ji;
-        }
-        const int M = fields_of<MT>(j.M);
-        const int nreq = KR == 1 ? 1 : j.n_req;
-        const int64_t r = (u - j.k1_unit0) * (kUpdThreads / kWave) + wv;
-        if (r >= j.n_runs) continue;
-        const ReqDev* rq = b.reqs + j.req0;
-        const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
-        const int64_t t_begin = r * j.tiles_per_run;
-        const int64_t t_end = min(j.n_tiles, t_begin + j.tiles_per_run);
-        const int64_t c_begin = t_begin * tile_cells;
-        const int64_t c_end = min(j.n, t_end * tile_cells);
-        const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
+    const int M = fields_of<MT>(j.M);
+    const int nreq = KR == 1 ? 1 : j.n_req;
+    const ReqDev* rq = b.reqs + j.req0;
+    const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
+    const int64_t t_begin = r * j.tiles_per_run;
+    const int64_t t_end = min(j.n_tiles, t_begin + j.tiles_per_run);
+    const int64_t c_begin = t_begin * tile_cells;
+    const int64_t c_end = min(j.n, t_end * tile_cells);
+    const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
 
-        ImpCtx ctx[KR];
-        RunAcc run[KR];
-        double prev[KR], tacc[KR];
+    ImpCtx ctx[KR];
+    RunAcc run[KR];
+    double prev[KR], tacc[KR];
 #pragma unroll
-        for (int q = 0; q < KR; ++q) {
-            if (q < nreq) ctx[q] = make_ctx(rq[q]);
-            run[q].init();
-            prev[q] = 0.0;
-            tacc[q] = 0.0;
+    for (int q = 0; q < KR; ++q) {
+        if (q < nreq) ctx[q] = make_ctx(rq[q]);
+        run[q].init();
+        prev[q] = 0.0;
+        tacc[q] = 0.0;
+    }
+    int64_t t = t_begin;
+    int in_tile = 0;
+    D cur[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) cur[g].load(j, M, ((c_begin + (int64_t)g * kStepCells) >> 2) + lane);
+    for (int s = 0; s < nsteps; s += G) {
+        D nxt[G];
+        if (s + G < nsteps) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) nxt[g].load(j, M, ((c_begin + (int64_t)(s + G + g) * kStepCells) >> 2) + lane);
         }
-        int64_t t = t_begin;
-        int in_tile = 0;
-        StepData<MT, S> cur;
-        cur.load(j, M, (c_begin >> 2) + lane);
-        for (int s = 0; s < nsteps; ++s) {
-            const int64_t quad = ((c_begin + (int64_t)s * kStepCells) >> 2) + lane;
-            StepData<MT, S> nxt;
-            if (s + 1 < nsteps) nxt.load(j, M, quad + kWave);
-            float x[MT][4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-#pragma unroll
-                for (int m = 0; m < MT; ++m) x[m][k] = m < M ? cur.q[m].get(k) : 0.0f;
+        for (int g = 0; g < G; ++g) {
+            if (s + g >= nsteps) break;
+            const int64_t quad = ((c_begin + (int64_t)(s + g) * kStepCells) >> 2) + lane;
 #pragma unroll
             for (int q = 0; q < KR; ++q) {
                 if (q < nreq) {
                     float f[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        float xk[MT];
-#pragma unroll
-                        for (int m = 0; m < MT; ++m) xk[m] = x[m][k];
-                        const float v = variation<MT>(xk, M, tf_lds + rq[q].tf_job_off, rq[q]);
-                        const float fk = importance_from_v(v, (cur.lv >> (8 * k)) & 0xFFu, ctx[q]);
+                        const float v = cell_v<MT>(cur[g], k, M, tf_lds + rq[q].tf_job_off, rq[q]);
+                        const float fk = importance_from_v(v, (cur[g].lv >> (8 * k)) & 0xFFu, ctx[q]);
                         f[k] = ((quad << 2) + k < j.n) ? fk : 0.0f;
                     }
                     tacc[q] += (double)((f[0] + f[1]) + (f[2] + f[3]));
                 }
             }
-            if (++in_tile == j.tile_steps || s + 1 == nsteps) {
+            if (++in_tile == j.tile_steps || s + g + 1 == nsteps) {
 #pragma unroll
                 for (int q = 0; q < KR; ++q) {
                     if (q < nreq) {
@@ -344,11 +398,33 @@ __global__ __launch_bounds__(kUpdThreads) void k_tile_sums(BatchDev b) {
                 ++t;
                 in_tile = 0;
             }
-            cur = nxt;
         }
 #pragma unroll
-        for (int q = 0; q < KR; ++q)
-            if (q < nreq && lane == 0) rq[q].ws.run_total[r] = fmax(prev[q], run[q].value(rq[q].scan_mode));
+        for (int g = 0; g < G; ++g) cur[g] = nxt[g];
+    }
+#pragma unroll
+    for (int q = 0; q < KR; ++q)
+        if (q < nreq && lane == 0) rq[q].ws.run_total[r] = fmax(prev[q], run[q].value(rq[q].scan_mode));
+}
+
+// A workgroup takes 4 consecutive runs of one job; wave r of the job owns the
+// tiles [r k, (r + 1) k).
+template <int MT, typename S, int KR, int IDX>
+__global__ __launch_bounds__(kUpdThreads) void k_tile_sums(BatchDev b) {
+    extern __shared__ float tf_lds[];
+    const int wv = threadIdx.x / kWave;
+    int loaded = -1;
+    for (int64_t u = blockIdx.x; u < b.k1_units; u += gridDim.x) {
+        const int ji = find_job_k1(b, u);
+        const JobDev& j = b.jobs[ji];
+        if ((j.idx[0] != nullptr) != (IDX != 0)) continue;
+        load_job_tables(j, ji, loaded, tf_lds);
+        const int64_t r = (u - j.k1_unit0) * (kUpdThreads / kWave) + wv;
+        if (r >= j.n_runs) continue;
+        if constexpr (IDX != 0)
+            tile_sums_run<MT, KR, StepIdx<MT>>(b, j, r, tf_lds);
+        else
+            tile_sums_run<MT, KR, StepData<MT, S>>(b, j, r, tf_lds);
     }
 }
 
@@ -684,6 +760,67 @@ __device__ void write_single(const ReqDev& q, int M, int key, const float (&x)[M
 
 constexpr int kBinThreads = 64;   // one wave per workgroup: each unit is one (request, tile)
 
+// Pixel interval [X0, X1] of tile t of request q, and its first and last bin.
+struct TileSpan {
+    double scale_d;
+    float scale_f, X0, X1;
+    int b0, b1;
+};
+
+__device__ __forceinline__ TileSpan tile_span(const ReqDev& q, const JobDev& j, int64_t t) {
+    TileSpan sp;
+    const bool degenerate = q.ws.scal[1] != 0.0;
+    sp.scale_d = (double)q.W / q.ws.scal[0];
+    sp.scale_f = (float)sp.scale_d;
+    sp.X0 = (float)(tile_offset(j, q.ws, t, degenerate) * sp.scale_d);
+    sp.X1 = (float)(tile_offset(j, q.ws, t + 1, degenerate) * sp.scale_d);
+    const int W1 = q.W - 1;
+    sp.b0 = max(0, min((int)floorf(sp.X0), W1));
+    sp.b1 = max(0, min((int)floorf(sp.X1), W1));
+    return sp;
+}
+
+// K3a.  A tile whose pixel interval lies inside one bin puts every cell in
+// that bin: its record is the tile's precomputed statistics and no cell is
+// read (the projection is hierarchical over tiles).  Other tiles are queued
+// for K3b, one wave-aggregated atomic per wave.
+__global__ __launch_bounds__(256) void k_classify(BatchDev bd) {
+    const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool need = false;
+    if (u < bd.k3_units) {
+        const ReqDev& q = bd.reqs[find_req_k3(bd, u)];
+        const JobDev& j = bd.jobs[q.job];
+        const int64_t t = u - q.k3_unit0;
+        const int64_t T = j.n_tiles;
+        const TileSpan sp = tile_span(q, j, t);
+        if (sp.b0 == sp.b1) {
+            const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
+            const int64_t tbase = t * tile_cells;
+            for (int m = 0; m < j.M; ++m) {
+                const int64_t o = (int64_t)m * T + t;    // head record of field m
+                q.ws.rec_sum[o] = j.agg_sum[o];
+                q.ws.rec_min[o] = j.agg_min[o];
+                q.ws.rec_max[o] = j.agg_max[o];
+            }
+            q.ws.rec_first[t] = (uint32_t)tbase;
+            q.ws.rec_last[t] = (uint32_t)(min(tbase + tile_cells, j.n) - 1);
+            q.ws.head_bin[t] = sp.b0;
+            q.ws.tail_bin[t] = sp.b0;
+        } else {
+            need = true;
+        }
+    }
+    const uint64_t mask = __ballot(need);
+    if (mask) {
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        uint32_t base = 0;
+        if (lane_id() == leader) base = atomicAdd(bd.rescan_count, (uint32_t)__popcll(mask));
+        base = readlane(base, leader);
+        if (need) bd.rescan_queue[base + (uint32_t)__popcll(mask & lanemask_lt())] = (uint64_t)u;
+    }
+}
+
+// K3b: the queued tiles, one wave each.
 template <int MT, typename S>
 __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
     extern __shared__ float lds[];
@@ -691,8 +828,10 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
     float* tf_lds = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + (kRedBytes + 15) / 16 * 16);
     const int lane = lane_id();
     int loaded = -1;
+    const int64_t n_queued = *bd.rescan_count;
 
-    for (int64_t u = blockIdx.x; u < bd.k3_units; u += gridDim.x) {
+    for (int64_t i = blockIdx.x; i < n_queued; i += gridDim.x) {
+        const int64_t u = (int64_t)bd.rescan_queue[i];
         const int qi = find_req_k3(bd, u);
         const ReqDev& q = bd.reqs[qi];
         const JobDev& j = bd.jobs[q.job];
@@ -700,38 +839,14 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
         const int M = fields_of<MT>(j.M);
         const int64_t T = j.n_tiles;
         const bool degenerate = q.ws.scal[1] != 0.0;
-        const double Ftot = q.ws.scal[0];
-        const double scale_d = (double)q.W / Ftot;
-        const float scale_f = (float)scale_d;
+        const TileSpan sp = tile_span(q, j, t);
+        const float scale_f = sp.scale_f, X0 = sp.X0, X1 = sp.X1;
         const int W1 = q.W - 1;
         const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
         const int64_t tbase = t * tile_cells;
-        const float X0 = (float)(tile_offset(j, q.ws, t, degenerate) * scale_d);
-        const float X1 = (float)(tile_offset(j, q.ws, t + 1, degenerate) * scale_d);
         const int64_t tend = min(tbase + tile_cells, j.n);
         const uint32_t last_valid = (uint32_t)(tend - 1);
         const int nsteps = (int)((tend - tbase + kStepCells - 1) / kStepCells);
-
-        // A tile whose pixel interval [X0, X1] lies inside one bin puts every
-        // cell in that bin: its record is the tile's precomputed statistics and
-        // no cell needs to be read (the projection is hierarchical over tiles).
-        const int b0 = max(0, min((int)floorf(X0), W1));
-        const int b1 = max(0, min((int)floorf(X1), W1));
-        if (b0 == b1) {
-            if (lane < M) {
-                const int64_t o = (int64_t)lane * T + t;   // head record of field `lane`
-                q.ws.rec_sum[o] = j.agg_sum[o];
-                q.ws.rec_min[o] = j.agg_min[o];
-                q.ws.rec_max[o] = j.agg_max[o];
-            }
-            if (lane == 0) {
-                q.ws.rec_first[t] = (uint32_t)tbase;
-                q.ws.rec_last[t] = last_valid;
-                q.ws.head_bin[t] = b0;
-                q.ws.tail_bin[t] = b0;
-            }
-            continue;
-        }
 
         // the tile is rescanned: this request's tables in LDS
         if (qi != loaded) {
@@ -1083,6 +1198,38 @@ dvl_status launch_tile_aggregates(int64_t n, int dtype, const void* field, int64
     return DVL_OK;
 }
 
+// ------------------------------------------------------------------ TF entry cache
+
+// entries of 4 consecutive cells per lane, packed into one 32-bit store
+template <typename S>
+__global__ __launch_bounds__(256) void k_build_index(int64_t n_quads, const void* __restrict__ field, float s,
+                                                     float b, float nmax, uint32_t* __restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_quads; i += stride) {
+        Quad<S> q;
+        q.load(field, i);
+        uint32_t w = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w |= (uint32_t)tf_entry(q.get(k), s, b, nmax) << (8 * k);
+        out[i] = w;
+    }
+}
+
+dvl_status launch_build_index(int64_t n_pad, int dtype, const void* field, float s, float b, int n_tf,
+                              uint8_t* out, int n_cu, hipStream_t st) {
+    const int64_t n_quads = n_pad / 4;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_quads + 255) / 256, (int64_t)n_cu * 16));
+    const float nmax = (float)(n_tf - 1);
+    if (dtype == DVL_F16)
+        hipLaunchKernelGGL(k_build_index<F16>, dim3(grid), dim3(256), 0, st, n_quads, field, s, b, nmax, (uint32_t*)out);
+    else if (dtype == DVL_BF16)
+        hipLaunchKernelGGL(k_build_index<BF16>, dim3(grid), dim3(256), 0, st, n_quads, field, s, b, nmax, (uint32_t*)out);
+    else
+        hipLaunchKernelGGL(k_build_index<F32>, dim3(grid), dim3(256), 0, st, n_quads, field, s, b, nmax, (uint32_t*)out);
+    DVL_HIP(hipGetLastError());
+    return DVL_OK;
+}
+
 // ------------------------------------------------------------------ launcher
 
 template <int MT, typename S, int KR>
@@ -1095,16 +1242,31 @@ static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEv
     const unsigned g1 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.k1_units, (int64_t)n_cu * 8));
     if (dvl_status st = mark(0)) return st;
     if (b.any_exact) {
-        hipLaunchKernelGGL((k_vmax_exact<MT, S, KR>), dim3(g1), dim3(kUpdThreads), lds1, s, b);
-        DVL_HIP(hipGetLastError());
+        if (b.paths & kPathValues) {
+            hipLaunchKernelGGL((k_vmax_exact<MT, S, KR, 0>), dim3(g1), dim3(kUpdThreads), lds1, s, b);
+            DVL_HIP(hipGetLastError());
+        }
+        if (b.paths & kPathEntries) {
+            hipLaunchKernelGGL((k_vmax_exact<MT, S, KR, 1>), dim3(g1), dim3(kUpdThreads), lds1, s, b);
+            DVL_HIP(hipGetLastError());
+        }
     }
     if (dvl_status st = mark(1)) return st;
-    hipLaunchKernelGGL((k_tile_sums<MT, S, KR>), dim3(g1), dim3(kUpdThreads), lds1, s, b);
-    DVL_HIP(hipGetLastError());
+    if (b.paths & kPathValues) {
+        hipLaunchKernelGGL((k_tile_sums<MT, S, KR, 0>), dim3(g1), dim3(kUpdThreads), lds1, s, b);
+        DVL_HIP(hipGetLastError());
+    }
+    if (b.paths & kPathEntries) {
+        hipLaunchKernelGGL((k_tile_sums<MT, S, KR, 1>), dim3(g1), dim3(kUpdThreads), lds1, s, b);
+        DVL_HIP(hipGetLastError());
+    }
     if (dvl_status st = mark(2)) return st;
     hipLaunchKernelGGL(k_carry, dim3((unsigned)b.n_reqs), dim3(kCarryThreads), 0, s, b);
     DVL_HIP(hipGetLastError());
     if (dvl_status st = mark(3)) return st;
+    const unsigned g3a = (unsigned)std::max<int64_t>(1, (b.k3_units + 255) / 256);
+    hipLaunchKernelGGL(k_classify, dim3(g3a), dim3(256), 0, s, b);
+    DVL_HIP(hipGetLastError());
     const size_t lds3 = (kRedBytes + 15) / 16 * 16 + (size_t)b.max_req_tf * sizeof(float);
     const unsigned g3 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.k3_units, (int64_t)n_cu * 16));
     hipLaunchKernelGGL((k_bin<MT, S>), dim3(g3), dim3(kBinThreads), lds3, s, b);

@@ -16,6 +16,8 @@ constexpr int kStepCells = kWave * kCellsPerLane;    // 256 cells per wave step
 constexpr int kDefaultTileSteps = 16;            // 4096-cell tiles unless tuned
 constexpr int kMaxReqPerJob = 8;
 constexpr int kPhases = 5;                       // exact vmax, tile sums, carry, bin, edges
+constexpr int kPathValues = 1;                   // jobs that read the field values
+constexpr int kPathEntries = 2;                  // jobs that read cached TF entries
 
 // Workspace of one request on a volume of T tiles and M fields.
 struct UpdWorkspace {
@@ -83,6 +85,7 @@ struct JobDev {
     int pad_;
     const uint8_t* level;
     const void* fields[kMaxFields];
+    const uint8_t* idx[kMaxFields];   // cached TF entries per field, or all NULL: read the values
     const double* agg_sum;    // per-tile field statistics [M][T]
     const float* agg_min;
     const float* agg_max;
@@ -92,12 +95,15 @@ struct JobDev {
 struct BatchDev {
     const JobDev* jobs;
     const ReqDev* reqs;
+    uint32_t* rescan_count;   // tiles queued for a rescan (0 when the descriptors are uploaded)
+    uint64_t* rescan_queue;   // [k3_units] projection units of the queued tiles
     int n_jobs;
     int n_reqs;
     int64_t k1_units;
     int64_t k3_units;
     int64_t k4_units;
     int any_exact;
+    int paths;                // kPathValues | kPathEntries: which importance-pass variants to launch
     int max_req_tf;           // largest request table block (floats): LDS of the projection
     int max_job_tf;           // largest job table block (floats): LDS of the importance pass
     int pad_;
@@ -108,6 +114,11 @@ struct BatchDev {
 // requests per job in the batch.  ev (optional): kPhases + 1 events.
 dvl_status launch_batch(const BatchDev& b, int dtype, int max_m, int max_req, int n_cu, hipStream_t s,
                         hipEvent_t* ev = nullptr);
+
+// TF entry of every cell of one sorted field under quantiser (s, b) with
+// n_tf <= 256 entries, one byte per cell, over all n_pad (padded) cells.
+dvl_status launch_build_index(int64_t n_pad, int dtype, const void* field, float s, float b, int n_tf,
+                              uint8_t* out, int n_cu, hipStream_t st);
 
 // Per-tile sum / min / max of one sorted field.
 dvl_status launch_tile_aggregates(int64_t n, int dtype, const void* field, int64_t n_tiles, int tile_steps,

@@ -22,6 +22,7 @@ OK, E_INVALID, E_NOMEM, E_HIP, E_STATE, E_OVERLAP, E_RANGE = range(7)
 F32, F16, BF16 = 0, 1, 2
 VMAX_TF_RANGE, VMAX_TF_BOUND, VMAX_EXACT = 0, 1, 2
 SCAN_FP64, SCAN_KAHAN_FP32, SCAN_NAIVE_FP32 = 0, 1, 2
+ENTRY_CACHE_AUTO, ENTRY_CACHE_ALWAYS, ENTRY_CACHE_NEVER = 0, 1, 2
 
 _DTYPE_CODE = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
 _CODE_DTYPE = {v: k for k, v in _DTYPE_CODE.items()}
@@ -46,7 +47,7 @@ class dvl_bins(C.Structure):
 
 
 class dvl_build_options(C.Structure):
-    _fields_ = [("tile_steps", C.c_int32), ("run_waves", C.c_int32)]
+    _fields_ = [("tile_steps", C.c_int32), ("run_waves", C.c_int32), ("entry_cache", C.c_int32)]
 
 
 class dvl_request(C.Structure):
@@ -94,6 +95,8 @@ def lib():
         "dvl_volume_bytes": (C.c_size_t, [vp]),
         "dvl_update_workspace_bytes": (C.c_size_t, [i64, i32, i32]),
         "dvl_destroy": (None, [vp]),
+        "dvl_set_entry_cache": (i32, [vp, i32]),
+        "dvl_entry_cache_info": (i32, [vp, vp, vp, vp]),
         "dvl_executor_create": (i32, [C.POINTER(vp)]),
         "dvl_executor_destroy": (None, [vp]),
         "dvl_executor_bytes": (C.c_size_t, [vp]),
@@ -169,9 +172,10 @@ def params(n_bins: int, exponent: float = 1.0, min_importance: float = 0.025,
 
 # ---------------------------------------------------------------- C-ABI mirrors
 
-def build_order(x, y, z, level, fields, stream=None, tile_steps: int = 0, run_waves: int = 0) -> "Volume":
-    """dvl_build_order (dvl_build_order_ex when tile_steps or run_waves is
-    given): one-time Hilbert ordering of the cells."""
+def build_order(x, y, z, level, fields, stream=None, tile_steps: int = 0, run_waves: int = 0,
+                entry_cache: int = ENTRY_CACHE_AUTO) -> "Volume":
+    """dvl_build_order (dvl_build_order_ex when an option is given): one-time
+    Hilbert ordering of the cells."""
     x, y, z = _dev(x, torch.int32), _dev(y, torch.int32), _dev(z, torch.int32)
     level = _dev(level, torch.uint8)
     fields = [_dev(f) for f in fields]
@@ -182,8 +186,8 @@ def build_order(x, y, z, level, fields, stream=None, tile_steps: int = 0, run_wa
         raise ValueError("fields must share one of float32 / float16 / bfloat16")
     arr = (C.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
     out = C.c_void_p()
-    if tile_steps or run_waves:
-        opt = dvl_build_options(int(tile_steps), int(run_waves))
+    if tile_steps or run_waves or entry_cache != ENTRY_CACHE_AUTO:
+        opt = dvl_build_options(int(tile_steps), int(run_waves), int(entry_cache))
         st = lib().dvl_build_order_ex(x.numel(), _ptr(x), _ptr(y), _ptr(z), _ptr(level), len(fields),
                                       _DTYPE_CODE[dt], C.cast(arr, C.c_void_p), C.byref(opt),
                                       _stream_ptr(stream), C.byref(out))
@@ -294,6 +298,20 @@ class Volume:
         _check(lib().dvl_export_sorted(self.handle, _ptr(level), C.cast(arr, C.c_void_p),
                                        _stream_ptr(stream)), "dvl_export_sorted")
         return level, fields
+
+    def set_entry_cache(self, policy: int):
+        """dvl_set_entry_cache: ENTRY_CACHE_AUTO / ALWAYS / NEVER (NEVER frees it)."""
+        _check(lib().dvl_set_entry_cache(self.handle, int(policy)), "dvl_set_entry_cache")
+
+    def entry_cache_info(self):
+        """None, or (lo, hi, n_tf) arrays of the windows the TF entry cache holds."""
+        M = self.m
+        lo, hi = np.zeros(M, np.float32), np.zeros(M, np.float32)
+        nt = np.zeros(M, np.int32)
+        P = lambda a: a.ctypes.data_as(C.c_void_p)
+        if not lib().dvl_entry_cache_info(self.handle, P(lo), P(hi), P(nt)):
+            return None
+        return lo, hi, nt
 
     def set_timing(self, enable: bool = True):
         """dvl_set_timing: record per-kernel HIP events on every update."""

@@ -57,23 +57,30 @@ def cfg4_sizes(n_vol: int = 32, lo: float = 1e6, hi: float = 20e6, seed: int | N
     return [float(v) for v in sizes], [int(v) for v in levels]
 
 
-def cfg4(device="cpu", n_vol: int = 32, scale: float = 1.0):
+def cfg4_volume(k: int, device="cpu", n_vol: int = 32, scale: float = 1.0) -> Volume:
+    """The k-th volume of the batch workload (8 fields)."""
     sizes, levels = cfg4_sizes(n_vol)
-    vols = []
-    for k, (n_t, nl) in enumerate(zip(sizes, levels)):
-        fr = (0.3,) * (nl - 1)
-        b = base_side_for(n_t * scale, fr)
-        vols.append(make_amr(b, fr, 8, config_seed(4) * 1000 + k, device, octaves=4, field_octaves=2))
-    return vols
+    fr = (0.3,) * (levels[k] - 1)
+    b = base_side_for(sizes[k] * scale, fr)
+    return make_amr(b, fr, 8, config_seed(4) * 1000 + k, device, octaves=4, field_octaves=2)
 
 
-def cfg5(device="cpu", scale: float = 1.0, sizes=(10e6, 50e6, 150e6, 300e6)):
-    vols = []
+def cfg4(device="cpu", n_vol: int = 32, scale: float = 1.0):
+    return [cfg4_volume(k, device, n_vol, scale) for k in range(n_vol)]
+
+
+CFG5_SIZES = (10e6, 50e6, 150e6, 300e6)
+
+
+def cfg5_volume(k: int, device="cpu", scale: float = 1.0, sizes=CFG5_SIZES) -> Volume:
+    """The k-th resident volume of the serving workload (4 levels)."""
     fr = (0.3, 0.3, 0.3)
-    for k, n_t in enumerate(sizes):
-        b = base_side_for(n_t * scale, fr)
-        vols.append(make_amr(b, fr, 4, config_seed(5) * 1000 + k, device, octaves=4, field_octaves=2))
-    return vols
+    b = base_side_for(sizes[k] * scale, fr)
+    return make_amr(b, fr, 4, config_seed(5) * 1000 + k, device, octaves=4, field_octaves=2)
+
+
+def cfg5(device="cpu", scale: float = 1.0, sizes=CFG5_SIZES):
+    return [cfg5_volume(k, device, scale, sizes) for k in range(len(sizes))]
 
 
 def tfs_for(i: int, n_fields: int, n_cp=(4, 4), n_tf: int = 256):

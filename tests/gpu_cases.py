@@ -74,13 +74,14 @@ def check_order(V, vol):
 def run_case(vol, alpha, W: int, exponent: float = 1.0, fmin: float = 0.025, vmax_mode: int = 0,
              clamp_mode: int = 0, level_scale: int = 1, scan_mode: int = 0,
              dtype=torch.float32, windows=None, label: str = "", check_order_too: bool = True,
-             edge_tol: float = 1e-6):
+             edge_tol: float = 1e-6, entry_cache: int = 0):
     D = dvl()
     print(f"[case] {label} n={vol.n} M={vol.m} W={W} p={exponent} fmin={fmin} vmax={vmax_mode} "
-          f"clamp={clamp_mode} lscale={level_scale} scan={scan_mode} dtype={dtype}", flush=True)
+          f"clamp={clamp_mode} lscale={level_scale} scan={scan_mode} dtype={dtype} cache={entry_cache}",
+          flush=True)
     dev = vol.to("cuda")
     fields = [f.to(dtype) for f in dev.fields]
-    V = D.build_order(dev.x, dev.y, dev.z, dev.level, fields)
+    V = D.build_order(dev.x, dev.y, dev.z, dev.level, fields, entry_cache=entry_cache)
     try:
         if check_order_too:
             o = check_order(V, vol)

@@ -108,6 +108,95 @@ def test_small_amr_params(exponent, fmin, vmax_mode, clamp, lscale, W):
              label=f"amr16 p={exponent}")
 
 
+@pytest.mark.parametrize("exponent,fmin,vmax_mode,clamp,lscale,W,dtype", [
+    (1.0, 0.025, 0, 0, 1, 1920, torch.float32),
+    (2.0, 0.025, 2, 0, 1, 777, torch.float32),
+    (0.5, 0.1, 1, 1, 3, 64, torch.float32),
+    (1.0, 0.025, 0, 0, 1, 1920, torch.float16),
+    (3.0, 0.0, 2, 0, 1, 300, torch.bfloat16),
+])
+def test_entry_cache_parity(exponent, fmin, vmax_mode, clamp, lscale, W, dtype):
+    """Updates that read the cached TF entries (built on first use) instead of
+    the values: same oracle parity."""
+    import synth
+    vol = synth.make_amr(16, (0.4, 0.3, 0.2), 4, 33, octaves=3, field_octaves=2)
+    run_case(vol, tfs(33, 4), W, exponent, fmin, vmax_mode, clamp, lscale, dtype=dtype, entry_cache=1,
+             label="entry cache")
+
+
+@pytest.mark.parametrize("n", [1, 255, 4097, 9000])
+def test_entry_cache_ragged(n):
+    vol = subset(random_amr(19, 16, 3, 0.3, n_fields=3), n, seed=n)
+    run_case(vol, tfs(n + 1, 3), 64, entry_cache=1, label=f"entry cache ragged {n}")
+
+
+def test_entry_cache_paths_agree_bitwise():
+    """The same updates through the value path, the automatic cache (built by
+    the second update with unchanged windows) and a cache rebuilt after a
+    window change give bitwise equal bins."""
+    import synth
+    D = dvl()
+    vol = synth.make_amr(16, (0.4, 0.3), 4, 63, octaves=3, field_octaves=2).to("cuda")
+    outs = {}
+    for policy in (D.ENTRY_CACHE_NEVER, D.ENTRY_CACHE_AUTO, D.ENTRY_CACHE_ALWAYS):
+        V = D.build_order(vol.x, vol.y, vol.z, vol.level, vol.fields, entry_cache=policy)
+        try:
+            res = []
+            for k in range(5):
+                A = tfs(700 + k, 4)
+                for m in range(4):
+                    lo, hi = V.field_range(m)
+                    if k == 3:                      # a window change, then back
+                        hi = hi * 0.5 + lo * 0.5
+                    D.set_tf(V, m, A[m], lo, hi)
+                b = D.Bins(1920, 4)
+                V.update(b, exponent=2.0)
+                res.append(V.read_bins(b))
+            outs[policy] = res
+        finally:
+            V.close()
+    for policy in (D.ENTRY_CACHE_AUTO, D.ENTRY_CACHE_ALWAYS):
+        for k in range(5):
+            for key in ("first", "last", "mean", "vmin", "vmax", "y", "f_total", "vmax_used"):
+                a, b = np.asarray(outs[policy][k][key]), np.asarray(outs[D.ENTRY_CACHE_NEVER][k][key])
+                assert a.tobytes() == b.tobytes(), (policy, k, key)
+
+
+def test_entry_cache_follows_set_field(cfg2_base64):
+    """A data change invalidates the cached entries."""
+    import synth
+    from parity import reconcile
+    D = dvl()
+    vol = cfg2_base64
+    dev = vol.to("cuda")
+    V = D.build_order(dev.x, dev.y, dev.z, dev.level, dev.fields, entry_cache=D.ENTRY_CACHE_ALWAYS)
+    try:
+        A = tfs(78, 4)
+        lo0 = [V.field_range(m)[0] for m in range(4)]
+        hi0 = [V.field_range(m)[1] for m in range(4)]
+        for m in range(4):
+            D.set_tf(V, m, A[m], lo0[m], hi0[m])
+        b = D.Bins(32, 4)
+        V.update(b)                      # builds the cache for these windows
+        V.read_bins(b)
+        new = dev.fields[1] * 0.5 + 0.25
+        V.set_field(1, new)
+        for m in range(4):               # same windows: a stale cache would be used if not invalidated
+            D.set_tf(V, m, A[m], lo0[m], hi0[m])
+        V.update(b)
+        g = V.read_bins(b)
+        fields = list(vol.fields)
+        fields[1] = new.cpu()
+        _, perm = V.export_order()
+        p = perm.cpu().numpy().view(np.uint32)
+        F = np.stack([f.numpy()[p] for f in fields])
+        lo, hi = np.array(lo0, np.float32), np.array(hi0, np.float32)
+        ob = oracle.update(vol.level.numpy()[p], F, A, lo, hi, 32, keep_cells=True)
+        reconcile(g, ob, F, A, lo, hi, 32)
+    finally:
+        V.close()
+
+
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
 def test_sixteen_bit_storage(dtype):
     import synth
