@@ -210,7 +210,7 @@ def main():
     ap.add_argument("--bins", type=int, default=1920)
     ap.add_argument("--exponent", type=float, default=1.0)
     ap.add_argument("--min-importance", type=float, default=0.025)
-    ap.add_argument("--cpu-sample", type=int, default=64_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=300_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES bytes (calibrates HBM byte counters)")

@@ -160,25 +160,40 @@ __device__ __forceinline__ float to_f32(BF16, uint16_t v) {
     return __uint_as_float((uint32_t)v << 16);
 }
 
+// Loads and stores through pointers known to address global memory.  The
+// kernels receive their buffers inside descriptor tables in memory, so the
+// compiler cannot infer the address space and would emit flat instructions,
+// which share the LDS counter: every wait for an LDS result would then also
+// wait for the outstanding prefetch loads.
+#define DVL_GLOBAL __attribute__((address_space(1)))
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ T gload(const void* base, int64_t i) {
+    return ((const DVL_GLOBAL T*)base)[i];
+}
+template <typename T>
+__device__ __forceinline__ void gstore(void* base, int64_t i, T v) {
+    ((DVL_GLOBAL T*)base)[i] = v;
+}
+
 // four consecutive values starting at a 4-aligned index
 template <typename S>
 struct Quad;
 template <>
 struct Quad<F32> {
-    float4 v;
-    __device__ __forceinline__ void load(const void* base, int64_t i4) {
-        v = reinterpret_cast<const float4*>(base)[i4];
-    }
+    f32x4 v;
+    __device__ __forceinline__ void load(const void* base, int64_t i4) { v = gload<f32x4>(base, i4); }
     __device__ __forceinline__ float get(int k) const {
         return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
     }
 };
 template <typename S16>
 struct Quad16 {
-    uint2 v;
-    __device__ __forceinline__ void load(const void* base, int64_t i4) {
-        v = reinterpret_cast<const uint2*>(base)[i4];
-    }
+    u32x2 v;
+    __device__ __forceinline__ void load(const void* base, int64_t i4) { v = gload<u32x2>(base, i4); }
     __device__ __forceinline__ float get(int k) const {
         const uint32_t w = k < 2 ? v.x : v.y;
         const uint16_t h = (uint16_t)((k & 1) ? (w >> 16) : (w & 0xFFFF));

@@ -107,7 +107,7 @@ struct ImpCtx {
 
 __device__ __forceinline__ ImpCtx make_ctx(const ReqDev& q) {
     ImpCtx c;
-    const float vm = *q.vmax_dev;
+    const float vm = gload<float>(q.vmax_dev, 0);
     c.inv_vmax = vm > 0.0f ? 1.0f / vm : 0.0f;
     c.fmin = q.fmin;
     c.p = q.exponent;
@@ -190,7 +190,7 @@ struct StepData {
 #pragma unroll
         for (int m = 0; m < MT; ++m)
             if (m < M) q[m].load(j.fields[m], quad);
-        lv = reinterpret_cast<const uint32_t*>(j.level)[quad];
+        lv = gload<uint32_t>(j.level, quad);
     }
 };
 
@@ -203,8 +203,8 @@ struct StepIdx {
     __device__ __forceinline__ void load(const JobDev& j, int M, int64_t quad) {
 #pragma unroll
         for (int m = 0; m < MT; ++m)
-            if (m < M) e[m] = reinterpret_cast<const uint32_t*>(j.idx[m])[quad];
-        lv = reinterpret_cast<const uint32_t*>(j.level)[quad];
+            if (m < M) e[m] = gload<uint32_t>(j.idx[m], quad);
+        lv = gload<uint32_t>(j.level, quad);
     }
 };
 
@@ -231,7 +231,7 @@ template <int MT> struct Group<StepIdx<MT>> { static constexpr int n = 4; };
 // ------------------------------------------------------------------ K0
 
 template <int MT, int KR, typename D>
-__device__ void vmax_run(const BatchDev& b, const JobDev& j, int64_t r, const float* tf_lds) {
+__device__ __forceinline__ void vmax_run(const BatchDev& b, const JobDev& j, int64_t r, const float* tf_lds) {
     constexpr int G = Group<D>::n;
     const int lane = lane_id();
     const int M = fields_of<MT>(j.M);
@@ -274,7 +274,7 @@ __device__ void vmax_run(const BatchDev& b, const JobDev& j, int64_t r, const fl
 __device__ __forceinline__ void load_job_tables(const JobDev& j, int ji, int& loaded, float* tf_lds) {
     if (ji != loaded) {
         __syncthreads();
-        for (int i = threadIdx.x; i < j.tf_total_all; i += blockDim.x) tf_lds[i] = j.tf_all[i];
+        for (int i = threadIdx.x; i < j.tf_total_all; i += blockDim.x) tf_lds[i] = gload<float>(j.tf_all, i);
         __syncthreads();
         loaded = ji;
     }
@@ -332,7 +332,7 @@ struct RunAcc {
 // and record, per request and tile, the non-decreasing sum of the earlier
 // tiles of the run.  Both sources give the same f bit for bit.
 template <int MT, int KR, typename D>
-__device__ void tile_sums_run(const BatchDev& b, const JobDev& j, int64_t r, const float* tf_lds) {
+__device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j, int64_t r, const float* tf_lds) {
     constexpr int G = Group<D>::n;
     const int lane = lane_id();
     const int M = fields_of<MT>(j.M);
@@ -391,7 +391,7 @@ __device__ void tile_sums_run(const BatchDev& b, const JobDev& j, int64_t r, con
                         const double ts = wave_sum_d(tacc[q]);
                         tacc[q] = 0.0;
                         prev[q] = fmax(prev[q], run[q].value(mode));
-                        if (lane == 0) rq[q].ws.local_prefix[t] = prev[q];
+                        if (lane == 0) gstore<double>(rq[q].ws.local_prefix, t, prev[q]);
                         run[q].add(mode, ts);
                     }
                 }
@@ -404,7 +404,7 @@ __device__ void tile_sums_run(const BatchDev& b, const JobDev& j, int64_t r, con
     }
 #pragma unroll
     for (int q = 0; q < KR; ++q)
-        if (q < nreq && lane == 0) rq[q].ws.run_total[r] = fmax(prev[q], run[q].value(rq[q].scan_mode));
+        if (q < nreq && lane == 0) gstore<double>(rq[q].ws.run_total, r, fmax(prev[q], run[q].value(rq[q].scan_mode)));
 }
 
 // A workgroup takes 4 consecutive runs of one job; wave r of the job owns the
@@ -504,7 +504,7 @@ __device__ void carry_scan(const ReqDev& q, int64_t T, int64_t n_cells) {
         const int64_t b0 = r0 + (int64_t)tid * kCarryItems;
         double v[kCarryItems];
 #pragma unroll
-        for (int k = 0; k < kCarryItems; ++k) v[k] = (b0 + k < T) ? ts[b0 + k] : 0.0;
+        for (int k = 0; k < kCarryItems; ++k) v[k] = (b0 + k < T) ? gload<double>(ts, b0 + k) : 0.0;
         Acc pre[kCarryItems];
         Acc run = Acc::zero();
 #pragma unroll
@@ -550,17 +550,17 @@ __device__ void carry_scan(const ReqDev& q, int64_t T, int64_t n_cells) {
 #pragma unroll
         for (int k = 0; k < kCarryItems; ++k) {
             c = fmax(c, fmin(tb + pre[k].value(), nb));
-            if (b0 + k < T) base_out[b0 + k] = c;
+            if (b0 + k < T) gstore<double>(base_out, b0 + k, c);
         }
         __syncthreads();
     }
     if (tid == 0) {
-        base_out[T] = round_end;
+        gstore<double>(base_out, T, round_end);
         // a zero total means every f was zero: fall back to f = 1 (linear map;
         // the projection then derives the tile offsets from the cell counts)
         const bool degenerate = !(round_end > 0.0);
-        q.ws.scal[0] = degenerate ? (double)n_cells : round_end;
-        q.ws.scal[1] = degenerate ? 1.0 : 0.0;
+        gstore<double>(q.ws.scal, 0, degenerate ? (double)n_cells : round_end);
+        gstore<double>(q.ws.scal, 1, degenerate ? 1.0 : 0.0);
     }
 }
 
@@ -637,10 +637,10 @@ __device__ __forceinline__ double tile_offset(const JobDev& j, const UpdWorkspac
                                               bool degenerate) {
     const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
     if (degenerate) return t >= j.n_tiles ? (double)j.n : (double)(t * tile_cells);
-    if (t >= j.n_tiles) return ws.run_base[j.n_runs];
+    if (t >= j.n_tiles) return gload<double>(ws.run_base, j.n_runs);
     const int64_t r = t / j.tiles_per_run;
-    const double lo = ws.run_base[r], hi = ws.run_base[r + 1];
-    return fmin(fmax(lo + ws.local_prefix[t], lo), hi);
+    const double lo = gload<double>(ws.run_base, r), hi = gload<double>(ws.run_base, r + 1);
+    return fmin(fmax(lo + gload<double>(ws.local_prefix, t), lo), hi);
 }
 
 // LDS scratch of the bin reductions of one wave: the partial statistics of up
@@ -714,26 +714,26 @@ __device__ void close_bin(const ReqDev& q, int M, int64_t T, RedScratch* rs, int
                 const float mean = (float)(sm / (double)cnt);
                 const int e = tf_entry(mean, q.s[m], q.b[m], q.nmax[m]);
                 const int64_t o = (int64_t)m * q.W + key;
-                q.mean[o] = mean;
-                q.vmin[o] = mn;
-                q.vmax[o] = mx;
-                q.y[o] = tf[q.tf_off[m] + e];
+                gstore<float>(q.mean, o, mean);
+                gstore<float>(q.vmin, o, mn);
+                gstore<float>(q.vmax, o, mx);
+                gstore<float>(q.y, o, tf[q.tf_off[m] + e]);
             } else {
                 const int64_t o = ((int64_t)(dest - 1) * M + m) * T + t;
-                q.ws.rec_sum[o] = sm;
-                q.ws.rec_min[o] = mn;
-                q.ws.rec_max[o] = mx;
+                gstore<double>(q.ws.rec_sum, o, sm);
+                gstore<float>(q.ws.rec_min, o, mn);
+                gstore<float>(q.ws.rec_max, o, mx);
             }
         }
         __builtin_amdgcn_wave_barrier();
     }
     if (lane == 0) {
         if (dest == 0) {
-            q.first_cell[key] = first;
-            q.last_cell[key] = last;
+            gstore<uint32_t>(q.first_cell, key, first);
+            gstore<uint32_t>(q.last_cell, key, last);
         } else {
-            q.ws.rec_first[(dest - 1) * T + t] = first;
-            q.ws.rec_last[(dest - 1) * T + t] = last;
+            gstore<uint32_t>(q.ws.rec_first, (dest - 1) * T + t, first);
+            gstore<uint32_t>(q.ws.rec_last, (dest - 1) * T + t, last);
         }
     }
 }
@@ -741,17 +741,17 @@ __device__ void close_bin(const ReqDev& q, int M, int64_t T, RedScratch* rs, int
 // a bin that holds one cell only (strictly inside a wide cell)
 template <int MT>
 __device__ void write_single(const ReqDev& q, int M, int key, const float (&x)[MT], uint32_t g, const float* tf) {
-    q.first_cell[key] = g;
-    q.last_cell[key] = g;
+    gstore<uint32_t>(q.first_cell, key, g);
+    gstore<uint32_t>(q.last_cell, key, g);
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         if (m < M) {
             const int e = tf_entry(x[m], q.s[m], q.b[m], q.nmax[m]);
             const int64_t o = (int64_t)m * q.W + key;
-            q.mean[o] = x[m];
-            q.vmin[o] = x[m];
-            q.vmax[o] = x[m];
-            q.y[o] = tf[q.tf_off[m] + e];
+            gstore<float>(q.mean, o, x[m]);
+            gstore<float>(q.vmin, o, x[m]);
+            gstore<float>(q.vmax, o, x[m]);
+            gstore<float>(q.y, o, tf[q.tf_off[m] + e]);
         }
     }
 }
@@ -769,8 +769,8 @@ struct TileSpan {
 
 __device__ __forceinline__ TileSpan tile_span(const ReqDev& q, const JobDev& j, int64_t t) {
     TileSpan sp;
-    const bool degenerate = q.ws.scal[1] != 0.0;
-    sp.scale_d = (double)q.W / q.ws.scal[0];
+    const bool degenerate = gload<double>(q.ws.scal, 1) != 0.0;
+    sp.scale_d = (double)q.W / gload<double>(q.ws.scal, 0);
     sp.scale_f = (float)sp.scale_d;
     sp.X0 = (float)(tile_offset(j, q.ws, t, degenerate) * sp.scale_d);
     sp.X1 = (float)(tile_offset(j, q.ws, t + 1, degenerate) * sp.scale_d);
@@ -798,14 +798,14 @@ __global__ __launch_bounds__(256) void k_classify(BatchDev bd) {
             const int64_t tbase = t * tile_cells;
             for (int m = 0; m < j.M; ++m) {
                 const int64_t o = (int64_t)m * T + t;    // head record of field m
-                q.ws.rec_sum[o] = j.agg_sum[o];
-                q.ws.rec_min[o] = j.agg_min[o];
-                q.ws.rec_max[o] = j.agg_max[o];
+                gstore<double>(q.ws.rec_sum, o, gload<double>(j.agg_sum, o));
+                gstore<float>(q.ws.rec_min, o, gload<float>(j.agg_min, o));
+                gstore<float>(q.ws.rec_max, o, gload<float>(j.agg_max, o));
             }
-            q.ws.rec_first[t] = (uint32_t)tbase;
-            q.ws.rec_last[t] = (uint32_t)(min(tbase + tile_cells, j.n) - 1);
-            q.ws.head_bin[t] = sp.b0;
-            q.ws.tail_bin[t] = sp.b0;
+            gstore<uint32_t>(q.ws.rec_first, t, (uint32_t)tbase);
+            gstore<uint32_t>(q.ws.rec_last, t, (uint32_t)(min(tbase + tile_cells, j.n) - 1));
+            gstore<int32_t>(q.ws.head_bin, t, sp.b0);
+            gstore<int32_t>(q.ws.tail_bin, t, sp.b0);
         } else {
             need = true;
         }
@@ -816,7 +816,7 @@ __global__ __launch_bounds__(256) void k_classify(BatchDev bd) {
         uint32_t base = 0;
         if (lane_id() == leader) base = atomicAdd(bd.rescan_count, (uint32_t)__popcll(mask));
         base = readlane(base, leader);
-        if (need) bd.rescan_queue[base + (uint32_t)__popcll(mask & lanemask_lt())] = (uint64_t)u;
+        if (need) gstore<uint64_t>(bd.rescan_queue, base + (uint32_t)__popcll(mask & lanemask_lt()), (uint64_t)u);
     }
 }
 
@@ -828,17 +828,17 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
     float* tf_lds = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + (kRedBytes + 15) / 16 * 16);
     const int lane = lane_id();
     int loaded = -1;
-    const int64_t n_queued = *bd.rescan_count;
+    const int64_t n_queued = gload<uint32_t>(bd.rescan_count, 0);
 
     for (int64_t i = blockIdx.x; i < n_queued; i += gridDim.x) {
-        const int64_t u = (int64_t)bd.rescan_queue[i];
+        const int64_t u = (int64_t)gload<uint64_t>(bd.rescan_queue, i);
         const int qi = find_req_k3(bd, u);
         const ReqDev& q = bd.reqs[qi];
         const JobDev& j = bd.jobs[q.job];
         const int64_t t = u - q.k3_unit0;
         const int M = fields_of<MT>(j.M);
         const int64_t T = j.n_tiles;
-        const bool degenerate = q.ws.scal[1] != 0.0;
+        const bool degenerate = gload<double>(q.ws.scal, 1) != 0.0;
         const TileSpan sp = tile_span(q, j, t);
         const float scale_f = sp.scale_f, X0 = sp.X0, X1 = sp.X1;
         const int W1 = q.W - 1;
@@ -851,7 +851,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
         // the tile is rescanned: this request's tables in LDS
         if (qi != loaded) {
             __builtin_amdgcn_wave_barrier();
-            for (int i = lane; i < q.tf_total; i += kWave) tf_lds[i] = q.tf[i];
+            for (int i = lane; i < q.tf_total; i += kWave) tf_lds[i] = gload<float>(q.tf, i);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -872,13 +872,14 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
             amax[m] = -INFINITY;
         }
 
-        StepData<MT, S> cur;
+        StepData<MT, S> cur, nx1;
         cur.load(j, M, (tbase >> 2) + lane);
+        if (nsteps > 1) nx1.load(j, M, (tbase >> 2) + kWave + lane);
         for (int s = 0; s < nsteps; ++s) {
             const int64_t c0 = tbase + (int64_t)s * kStepCells;
             const int64_t quad = (c0 >> 2) + lane;
             StepData<MT, S> nxt;
-            if (s + 1 < nsteps) nxt.load(j, M, quad + kWave);
+            if (s + 2 < nsteps) nxt.load(j, M, quad + 2 * kWave);
 
             float x[MT][4];
             float f[4];
@@ -945,7 +946,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
                         amax[m] = fmaxf(amax[m], fmaxf(fmaxf(x[m][0], x[m][1]), fmaxf(x[m][2], x[m][3])));
                     }
                 }
-                cur = nxt;
+                cur = nx1;
+                nx1 = nxt;
                 continue;
             }
 
@@ -1030,15 +1032,16 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
                 b = wave_min_i32(nk);
                 if (b == INT_MAX) break;   // cannot happen: key_last is above
             }
-            cur = nxt;
+            cur = nx1;
+            nx1 = nxt;
         }
 
         // tile end: the open bin is the tile's last bin
         if (o_valid) {
             close_bin<MT>(q, M, T, rs, O == Bh ? 1 : 2, t, O, O_first, O_last, asum, amin, amax, tf_lds);
             if (lane == 0) {
-                q.ws.head_bin[t] = Bh;
-                q.ws.tail_bin[t] = O;
+                gstore<int32_t>(q.ws.head_bin, t, Bh);
+                gstore<int32_t>(q.ws.tail_bin, t, O);
             }
         }
     }
@@ -1057,8 +1060,8 @@ __global__ __launch_bounds__(256) void k_edges(BatchDev bd) {
     const int M = fields_of<MT>(j.M);
     const int b = (int)(u - q.k4_unit0);
     if (b == 0 && lane == 0) {
-        *q.f_total = q.ws.scal[0];
-        *q.vmax_used = *q.vmax_dev;
+        gstore<double>(q.f_total, 0, gload<double>(q.ws.scal, 0));
+        gstore<float>(q.vmax_used, 0, gload<float>(q.vmax_dev, 0));
     }
     const int64_t T = j.n_tiles;
     const int32_t* hb = q.ws.head_bin;
@@ -1067,14 +1070,14 @@ __global__ __launch_bounds__(256) void k_edges(BatchDev bd) {
     int64_t lo = 0, hi = T;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if (tb[mid] < b) lo = mid + 1; else hi = mid;
+        if (gload<int32_t>(tb, mid) < b) lo = mid + 1; else hi = mid;
     }
     const int64_t t0 = lo;
     lo = 0;
     hi = T;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if (hb[mid] <= b) lo = mid + 1; else hi = mid;
+        if (gload<int32_t>(hb, mid) <= b) lo = mid + 1; else hi = mid;
     }
     const int64_t t1 = lo - 1;
     if (t0 <= t1 && t0 == t1 && hb[t0] < b && b < tb[t0]) return;  // finalised by the projection pass
@@ -1082,18 +1085,18 @@ __global__ __launch_bounds__(256) void k_edges(BatchDev bd) {
     Seg<MT> acc;
     seg_clear(acc);
     for (int64_t t = t0 + lane; t <= t1; t += kWave) {
-        const int r = hb[t] == b ? 0 : (tb[t] == b ? 1 : -1);
+        const int r = gload<int32_t>(hb, t) == b ? 0 : (gload<int32_t>(tb, t) == b ? 1 : -1);
         if (r < 0) continue;
         Seg<MT> s;
-        s.first = q.ws.rec_first[r * T + t];
-        s.last = q.ws.rec_last[r * T + t];
+        s.first = gload<uint32_t>(q.ws.rec_first, r * T + t);
+        s.last = gload<uint32_t>(q.ws.rec_last, r * T + t);
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             if (m < M) {
                 const int64_t o = ((int64_t)r * M + m) * T + t;
-                s.sum[m] = q.ws.rec_sum[o];
-                s.mn[m] = q.ws.rec_min[o];
-                s.mx[m] = q.ws.rec_max[o];
+                s.sum[m] = gload<double>(q.ws.rec_sum, o);
+                s.mn[m] = gload<float>(q.ws.rec_min, o);
+                s.mx[m] = gload<float>(q.ws.rec_max, o);
             } else {
                 s.sum[m] = 0.0;
                 s.mn[m] = INFINITY;
@@ -1113,28 +1116,28 @@ __global__ __launch_bounds__(256) void k_edges(BatchDev bd) {
     acc.last = wave_max_u32(acc.last);
     if (lane != 0) return;
     if (acc.first == 0xFFFFFFFFu) {  // no cell (cannot happen with a positive total width)
-        q.first_cell[b] = 0xFFFFFFFFu;
-        q.last_cell[b] = 0xFFFFFFFEu;
+        gstore<uint32_t>(q.first_cell, b, 0xFFFFFFFFu);
+        gstore<uint32_t>(q.last_cell, b, 0xFFFFFFFEu);
         for (int m = 0; m < M; ++m) {
             const int64_t o = (int64_t)m * q.W + b;
-            q.mean[o] = 0.0f;
-            q.vmin[o] = INFINITY;
-            q.vmax[o] = -INFINITY;
-            q.y[o] = 0.0f;
+            gstore<float>(q.mean, o, 0.0f);
+            gstore<float>(q.vmin, o, INFINITY);
+            gstore<float>(q.vmax, o, -INFINITY);
+            gstore<float>(q.y, o, 0.0f);
         }
         return;
     }
     const uint32_t cnt = acc.last - acc.first + 1u;
-    q.first_cell[b] = acc.first;
-    q.last_cell[b] = acc.last;
+    gstore<uint32_t>(q.first_cell, b, acc.first);
+    gstore<uint32_t>(q.last_cell, b, acc.last);
     for (int m = 0; m < M; ++m) {
         const float mean = (float)(acc.sum[m] / (double)cnt);
         const int e = tf_entry(mean, q.s[m], q.b[m], q.nmax[m]);
         const int64_t o = (int64_t)m * q.W + b;
-        q.mean[o] = mean;
-        q.vmin[o] = acc.mn[m];
-        q.vmax[o] = acc.mx[m];
-        q.y[o] = q.tf[q.tf_off[m] + e];
+        gstore<float>(q.mean, o, mean);
+        gstore<float>(q.vmin, o, acc.mn[m]);
+        gstore<float>(q.vmax, o, acc.mx[m]);
+        gstore<float>(q.y, o, gload<float>(q.tf, q.tf_off[m] + e));
     }
 }
 
