@@ -178,22 +178,50 @@ template <typename T>
 __device__ __forceinline__ void gstore(void* base, int64_t i, T v) {
     ((DVL_GLOBAL T*)base)[i] = v;
 }
+// scalar base + 32-bit byte offset: one global load with a scalar address
+template <typename T>
+__device__ __forceinline__ T gload_at(const char* base, uint32_t byte_off) {
+    return *(const DVL_GLOBAL T*)(base + byte_off);
+}
+
+// Values that are the same in every lane (descriptor fields) moved to scalar
+// registers, so that branches on them are scalar branches and addresses built
+// from them use scalar bases.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ float uni(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int64_t uni(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T* uni(T* p) {
+    return reinterpret_cast<T*>(uni((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
 
 // four consecutive values starting at a 4-aligned index
 template <typename S>
 struct Quad;
 template <>
 struct Quad<F32> {
+    static constexpr uint32_t kBytes = 16;
     f32x4 v;
     __device__ __forceinline__ void load(const void* base, int64_t i4) { v = gload<f32x4>(base, i4); }
+    __device__ __forceinline__ void load_at(const char* base, uint32_t off) { v = gload_at<f32x4>(base, off); }
     __device__ __forceinline__ float get(int k) const {
         return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
     }
 };
 template <typename S16>
 struct Quad16 {
+    static constexpr uint32_t kBytes = 8;
     u32x2 v;
     __device__ __forceinline__ void load(const void* base, int64_t i4) { v = gload<u32x2>(base, i4); }
+    __device__ __forceinline__ void load_at(const char* base, uint32_t off) { v = gload_at<u32x2>(base, off); }
     __device__ __forceinline__ float get(int k) const {
         const uint32_t w = k < 2 ? v.x : v.y;
         const uint16_t h = (uint16_t)((k & 1) ? (w >> 16) : (w & 0xFFFF));

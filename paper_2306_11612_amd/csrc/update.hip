@@ -107,13 +107,13 @@ struct ImpCtx {
 
 __device__ __forceinline__ ImpCtx make_ctx(const ReqDev& q) {
     ImpCtx c;
-    const float vm = gload<float>(q.vmax_dev, 0);
+    const float vm = uni(gload<float>(q.vmax_dev, 0));
     c.inv_vmax = vm > 0.0f ? 1.0f / vm : 0.0f;
-    c.fmin = q.fmin;
-    c.p = q.exponent;
-    c.exp_is_one = q.exp_is_one;
-    c.clamp_mode = q.clamp_mode;
-    c.lshift = q.level_shift;
+    c.fmin = uni(q.fmin);
+    c.p = uni(q.exponent);
+    c.exp_is_one = uni(q.exp_is_one);
+    c.clamp_mode = uni(q.clamp_mode);
+    c.lshift = uni(q.level_shift);
     return c;
 }
 
@@ -141,16 +141,17 @@ __device__ __forceinline__ float variation(const float (&x)[MT], int M, const fl
     return amax - amin;
 }
 
-// Eq. 1 from cached TF entries: byte k of packed[m] is the entry of cell k
+// Eq. 1 from cached TF entries: byte k of packed[m] is the entry of cell k,
+// off[m] the start of field m's table in `tf`
 template <int MT>
 __device__ __forceinline__ float variation_idx(const uint32_t (&packed)[MT], int k, int M,
-                                               const float* __restrict__ tf, const ReqDev& q) {
+                                               const float* __restrict__ tf, const int (&off)[MT]) {
     float amax = -INFINITY, amin = INFINITY;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         if (m < M) {
             const int e = (int)((packed[m] >> (8 * k)) & 0xFFu);
-            const float al = tf[q.tf_off[m] + e];
+            const float al = tf[off[m] + e];
             amax = fmaxf(amax, al);
             amin = fminf(amin, al);
         }
@@ -181,9 +182,19 @@ __device__ __forceinline__ int fields_of(int M) {
     return MT <= 8 ? MT : M;
 }
 
+// A wave's streams over one run of a job: scalar base pointers advanced to
+// the run's first cell, so every load is a scalar base plus a 32-bit lane
+// offset (a run holds at most 1/64 of a volume, well below 2^32 bytes).
+template <int MT>
+struct RunView {
+    const char* base[MT];
+    const char* lev;
+};
+
 // values of the 4 cells of this lane in the given step
 template <int MT, typename S>
 struct StepData {
+    static constexpr uint32_t kQuadBytes = Quad<S>::kBytes;
     Quad<S> q[MT];
     uint32_t lv;
     __device__ __forceinline__ void load(const JobDev& j, int M, int64_t quad) {
@@ -192,33 +203,64 @@ struct StepData {
             if (m < M) q[m].load(j.fields[m], quad);
         lv = gload<uint32_t>(j.level, quad);
     }
+    __device__ static const void* source(const JobDev& j, int m) { return j.fields[m]; }
+    // qd: quad index from the run's first cell
+    __device__ __forceinline__ void load(const RunView<MT>& v, int M, uint32_t qd) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            if (m < M) q[m].load_at(v.base[m], qd * kQuadBytes);
+        lv = gload_at<uint32_t>(v.lev, qd * 4u);
+    }
 };
 
 // TF entries of the 4 cells of this lane in the given step, from the
 // volume's entry cache (one byte per cell and field)
 template <int MT>
 struct StepIdx {
+    static constexpr uint32_t kQuadBytes = 4;
     uint32_t e[MT];
     uint32_t lv;
-    __device__ __forceinline__ void load(const JobDev& j, int M, int64_t quad) {
+    __device__ static const void* source(const JobDev& j, int m) { return j.idx[m]; }
+    __device__ __forceinline__ void load(const RunView<MT>& v, int M, uint32_t qd) {
 #pragma unroll
         for (int m = 0; m < MT; ++m)
-            if (m < M) e[m] = gload<uint32_t>(j.idx[m], quad);
-        lv = gload<uint32_t>(j.level, quad);
+            if (m < M) e[m] = gload_at<uint32_t>(v.base[m], qd * 4u);
+        lv = gload_at<uint32_t>(v.lev, qd * 4u);
     }
 };
 
-// V of cell k of this lane for request q, from values or from cached entries
+template <int MT, typename D>
+__device__ __forceinline__ RunView<MT> run_view(const JobDev& j, int M, int64_t c_begin) {
+    RunView<MT> v;
+    const int64_t quad0 = c_begin >> 2;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+        v.base[m] = m < M ? uni(reinterpret_cast<const char*>(D::source(j, m))) + quad0 * D::kQuadBytes : nullptr;
+    v.lev = uni(reinterpret_cast<const char*>(j.level)) + quad0 * 4;
+    return v;
+}
+
+// V of cell k of this lane for request q, from values or from cached
+// entries; off[m]: start of field m's table in `tf` (the request's block)
 template <int MT, typename S>
-__device__ __forceinline__ float cell_v(const StepData<MT, S>& d, int k, int M, const float* tf, const ReqDev& q) {
+__device__ __forceinline__ float cell_v(const StepData<MT, S>& d, int k, int M, const float* tf, const ReqDev& q,
+                                        const int (&off)[MT]) {
     float xk[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) xk[m] = m < M ? d.q[m].get(k) : 0.0f;
     return variation<MT>(xk, M, tf, q);
 }
 template <int MT>
-__device__ __forceinline__ float cell_v(const StepIdx<MT>& d, int k, int M, const float* tf, const ReqDev& q) {
-    return variation_idx<MT>(d.e, k, M, tf, q);
+__device__ __forceinline__ float cell_v(const StepIdx<MT>& d, int k, int M, const float* tf, const ReqDev& q,
+                                        const int (&off)[MT]) {
+    return variation_idx<MT>(d.e, k, M, tf, off);
+}
+
+// a request's table offsets, in scalar registers
+template <int MT>
+__device__ __forceinline__ void table_offsets(const ReqDev& q, int M, int (&off)[MT]) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) off[m] = m < M ? uni(q.tf_off[m]) : 0;
 }
 
 // How many steps one loop iteration loads ahead: one 4-vector per field is
@@ -234,30 +276,39 @@ template <int MT, int KR, typename D>
 __device__ __forceinline__ void vmax_run(const BatchDev& b, const JobDev& j, int64_t r, const float* tf_lds) {
     constexpr int G = Group<D>::n;
     const int lane = lane_id();
-    const int M = fields_of<MT>(j.M);
-    const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
-    const int64_t c_begin = r * j.tiles_per_run * tile_cells;
-    const int64_t c_end = min(j.n, (r + 1) * j.tiles_per_run * tile_cells);
+    const int M = uni(fields_of<MT>(j.M));
+    const int64_t n = uni(j.n);
+    const int64_t tile_cells = (int64_t)uni(j.tile_steps) * kStepCells;
+    const int64_t c_begin = r * uni(j.tiles_per_run) * tile_cells;
+    const int64_t c_end = min(n, (r + 1) * uni(j.tiles_per_run) * tile_cells);
     const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
-    const ReqDev* rq = b.reqs + j.req0;
+    const ReqDev* rq = b.reqs + uni(j.req0);
     float vmax[KR];
+    int toff[KR], off[KR][MT];
 #pragma unroll
-    for (int q = 0; q < KR; ++q) vmax[q] = 0.0f;
+    for (int q = 0; q < KR; ++q) {
+        vmax[q] = 0.0f;
+        if (q < j.n_req) {
+            toff[q] = uni(rq[q].tf_job_off);
+            table_offsets<MT>(rq[q], M, off[q]);
+        }
+    }
+    const RunView<MT> view = run_view<MT, D>(j, M, c_begin);
     for (int s = 0; s < nsteps; s += G) {
         D d[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) d[g].load(j, M, ((c_begin + (int64_t)(s + g) * kStepCells) >> 2) + lane);
+        for (int g = 0; g < G; ++g) d[g].load(view, M, (uint32_t)((s + g) * kWave + lane));
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (s + g >= nsteps) break;
             const int64_t quad = ((c_begin + (int64_t)(s + g) * kStepCells) >> 2) + lane;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if ((quad << 2) + k >= j.n) continue;
+                if ((quad << 2) + k >= n) continue;
 #pragma unroll
                 for (int q = 0; q < KR; ++q)
                     if (q < j.n_req && rq[q].vmax_exact)
-                        vmax[q] = fmaxf(vmax[q], cell_v<MT>(d[g], k, M, tf_lds + rq[q].tf_job_off, rq[q]));
+                        vmax[q] = fmaxf(vmax[q], cell_v<MT>(d[g], k, M, tf_lds + toff[q], rq[q], off[q]));
             }
         }
     }
@@ -284,7 +335,7 @@ __device__ __forceinline__ void load_job_tables(const JobDev& j, int ji, int& lo
 template <int MT, typename S, int KR, int IDX>
 __global__ __launch_bounds__(kUpdThreads) void k_vmax_exact(BatchDev b) {
     extern __shared__ float tf_lds[];
-    const int wv = threadIdx.x / kWave;
+    const int wv = uni((int)(threadIdx.x / kWave));
     int loaded = -1;
     for (int64_t u = blockIdx.x; u < b.k1_units; u += gridDim.x) {
         const int ji = find_job_k1(b, u);
@@ -335,37 +386,46 @@ template <int MT, int KR, typename D>
 __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j, int64_t r, const float* tf_lds) {
     constexpr int G = Group<D>::n;
     const int lane = lane_id();
-    const int M = fields_of<MT>(j.M);
-    const int nreq = KR == 1 ? 1 : j.n_req;
-    const ReqDev* rq = b.reqs + j.req0;
-    const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
-    const int64_t t_begin = r * j.tiles_per_run;
-    const int64_t t_end = min(j.n_tiles, t_begin + j.tiles_per_run);
+    const int M = uni(fields_of<MT>(j.M));
+    const int nreq = KR == 1 ? 1 : uni(j.n_req);
+    const ReqDev* rq = b.reqs + uni(j.req0);
+    const int tile_steps = uni(j.tile_steps);
+    const int64_t n = uni(j.n);
+    const int64_t tile_cells = (int64_t)tile_steps * kStepCells;
+    const int64_t t_begin = r * uni(j.tiles_per_run);
+    const int64_t t_end = min(uni(j.n_tiles), t_begin + uni(j.tiles_per_run));
     const int64_t c_begin = t_begin * tile_cells;
-    const int64_t c_end = min(j.n, t_end * tile_cells);
+    const int64_t c_end = min(n, t_end * tile_cells);
     const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
 
     ImpCtx ctx[KR];
     RunAcc run[KR];
     double prev[KR], tacc[KR];
+    int toff[KR], off[KR][MT];
 #pragma unroll
     for (int q = 0; q < KR; ++q) {
-        if (q < nreq) ctx[q] = make_ctx(rq[q]);
+        if (q < nreq) {
+            ctx[q] = make_ctx(rq[q]);
+            toff[q] = uni(rq[q].tf_job_off);
+            table_offsets<MT>(rq[q], M, off[q]);
+        }
         run[q].init();
         prev[q] = 0.0;
         tacc[q] = 0.0;
     }
     int64_t t = t_begin;
     int in_tile = 0;
+    const RunView<MT> view = run_view<MT, D>(j, M, c_begin);
     D cur[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) cur[g].load(j, M, ((c_begin + (int64_t)g * kStepCells) >> 2) + lane);
+    for (int g = 0; g < G; ++g) cur[g].load(view, M, (uint32_t)(g * kWave + lane));
     for (int s = 0; s < nsteps; s += G) {
+        // the next group, unconditionally (the last group reloads the last
+        // step): a conditional load would make the compiler wait for all
+        // outstanding loads before using the current group
         D nxt[G];
-        if (s + G < nsteps) {
 #pragma unroll
-            for (int g = 0; g < G; ++g) nxt[g].load(j, M, ((c_begin + (int64_t)(s + G + g) * kStepCells) >> 2) + lane);
-        }
+        for (int g = 0; g < G; ++g) nxt[g].load(view, M, (uint32_t)(min(s + G + g, nsteps - 1) * kWave + lane));
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (s + g >= nsteps) break;
@@ -376,14 +436,14 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
                     float f[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const float v = cell_v<MT>(cur[g], k, M, tf_lds + rq[q].tf_job_off, rq[q]);
+                        const float v = cell_v<MT>(cur[g], k, M, tf_lds + toff[q], rq[q], off[q]);
                         const float fk = importance_from_v(v, (cur[g].lv >> (8 * k)) & 0xFFu, ctx[q]);
-                        f[k] = ((quad << 2) + k < j.n) ? fk : 0.0f;
+                        f[k] = ((quad << 2) + k < n) ? fk : 0.0f;
                     }
                     tacc[q] += (double)((f[0] + f[1]) + (f[2] + f[3]));
                 }
             }
-            if (++in_tile == j.tile_steps || s + g + 1 == nsteps) {
+            if (++in_tile == tile_steps || s + g + 1 == nsteps) {
 #pragma unroll
                 for (int q = 0; q < KR; ++q) {
                     if (q < nreq) {
@@ -412,7 +472,7 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
 template <int MT, typename S, int KR, int IDX>
 __global__ __launch_bounds__(kUpdThreads) void k_tile_sums(BatchDev b) {
     extern __shared__ float tf_lds[];
-    const int wv = threadIdx.x / kWave;
+    const int wv = uni((int)(threadIdx.x / kWave));
     int loaded = -1;
     for (int64_t u = blockIdx.x; u < b.k1_units; u += gridDim.x) {
         const int ji = find_job_k1(b, u);
