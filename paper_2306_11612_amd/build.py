@@ -22,9 +22,8 @@ ARCH = os.environ.get("DVL_OFFLOAD_ARCH", "gfx950")
 # Kernels whose inputs are NaN-free by contract (build_order rejects NaN field
 # values) drop IEEE NaN handling of min/max, which otherwise doubles every
 # fminf/fmaxf with canonicalisations.  Host code keeps full IEEE semantics.
-FILE_FLAGS = {
-    "update.hip": ["-Xarch_device", "-fno-honor-nans", "-Xarch_device", "-mno-amdgpu-ieee"],
-}
+_NO_NAN = ["-Xarch_device", "-fno-honor-nans", "-Xarch_device", "-mno-amdgpu-ieee"]
+FILE_FLAGS = {f: _NO_NAN for f in ("update.hip", "update_f32.hip", "update_f16.hip", "update_bf16.hip")}
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -41,7 +40,7 @@ def _hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 6) -> str:
     """Compile all sources (always; object files are rebuilt in parallel) and link."""
     os.makedirs(OUT_DIR, exist_ok=True)
     obj_dir = os.path.join(OUT_DIR, "obj")

@@ -580,6 +580,7 @@ static BatchDev batch_dev(const Plan& P, char* d, int paths) {
     b.any_exact = P.any_exact;
     b.max_req_tf = P.max_req_tf;
     b.max_job_tf = P.max_job_tf;
+    b.max_req_job = P.max_req;
     return b;
 }
 

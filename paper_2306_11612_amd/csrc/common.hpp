@@ -181,7 +181,8 @@ __device__ __forceinline__ void gstore(void* base, int64_t i, T v) {
 // scalar base + 32-bit byte offset: one global load with a scalar address
 template <typename T>
 __device__ __forceinline__ T gload_at(const char* base, uint32_t byte_off) {
-    return *(const DVL_GLOBAL T*)(base + byte_off);
+    const DVL_GLOBAL char* g = (const DVL_GLOBAL char*)base;
+    return *(const DVL_GLOBAL T*)(g + byte_off);
 }
 
 // Values that are the same in every lane (descriptor fields) moved to scalar

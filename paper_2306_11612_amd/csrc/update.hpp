@@ -18,6 +18,7 @@ constexpr int kMaxReqPerJob = 8;
 constexpr int kPhases = 5;                       // exact vmax, tile sums, carry, bin, edges
 constexpr int kPathValues = 1;                   // jobs that read the field values
 constexpr int kPathEntries = 2;                  // jobs that read cached TF entries
+constexpr int kIdxTable = 256;                   // LDS floats per table on the cached-entry path
 
 // Workspace of one request on a volume of T tiles and M fields.
 struct UpdWorkspace {
@@ -106,7 +107,7 @@ struct BatchDev {
     int paths;                // kPathValues | kPathEntries: which importance-pass variants to launch
     int max_req_tf;           // largest request table block (floats): LDS of the projection
     int max_job_tf;           // largest job table block (floats): LDS of the importance pass
-    int pad_;
+    int max_req_job;          // most requests in one job
 };
 
 // Launch the five phases for the batch described by `b` (descriptors already

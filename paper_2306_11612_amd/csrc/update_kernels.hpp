@@ -1,0 +1,988 @@
+// Device code of the per-update kernels that depend on the field storage
+// type (K0 exact max V, K1 importance and tile sums, K3b rescan), their
+// helpers, and the templated launcher.  Each storage type is instantiated in
+// its own translation unit (update_f32.hip, update_f16.hip, update_bf16.hip);
+// the storage-independent kernels and the per-kernel commentary are in
+// update.hip.
+#pragma once
+
+#include "update.hpp"
+
+#include <algorithm>
+#include <climits>
+
+namespace dvl {
+
+// ------------------------------------------------------------------ unit lookup
+
+// last job whose first importance-pass unit is <= u
+__device__ __forceinline__ int find_job_k1(const BatchDev& b, int64_t u) {
+    int lo = 0, hi = b.n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.jobs[mid].k1_unit0 <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int find_req_k3(const BatchDev& b, int64_t u) {
+    int lo = 0, hi = b.n_reqs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.reqs[mid].k3_unit0 <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int find_req_k4(const BatchDev& b, int64_t u) {
+    int lo = 0, hi = b.n_reqs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.reqs[mid].k4_unit0 <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ per-cell math
+
+struct ImpCtx {
+    float inv_vmax;
+    float fmin;
+    float p;
+    int exp_is_one;
+    int clamp_mode;
+    int lshift;
+};
+
+__device__ __forceinline__ ImpCtx make_ctx(const ReqDev& q) {
+    ImpCtx c;
+    const float vm = uni(gload<float>(q.vmax_dev, 0));
+    c.inv_vmax = vm > 0.0f ? 1.0f / vm : 0.0f;
+    c.fmin = uni(q.fmin);
+    c.p = uni(q.exponent);
+    c.exp_is_one = uni(q.exp_is_one);
+    c.clamp_mode = uni(q.clamp_mode);
+    c.lshift = uni(q.level_shift);
+    return c;
+}
+
+// TF entry: clamp(floor(fma(x, s, b)), 0, n_tf - 1)
+__device__ __forceinline__ int tf_entry(float x, float s, float b, float nmax) {
+    float t = fmaf(x, s, b);
+    t = fminf(fmaxf(t, 0.0f), nmax);
+    return (int)t;
+}
+
+// Eq. 1: V = max_m alpha_m(x_m) - min_m alpha_m(x_m); `tf` is the request's block
+template <int MT>
+__device__ __forceinline__ float variation(const float (&x)[MT], int M, const float* __restrict__ tf,
+                                           const ReqDev& q) {
+    float amax = -INFINITY, amin = INFINITY;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        if (m < M) {
+            const int e = tf_entry(x[m], q.s[m], q.b[m], q.nmax[m]);
+            const float al = tf[q.tf_off[m] + e];
+            amax = fmaxf(amax, al);
+            amin = fminf(amin, al);
+        }
+    }
+    return amax - amin;
+}
+
+// Eq. 3 with the minimum importance
+__device__ __forceinline__ float importance_from_v(float v, uint32_t L, const ImpCtx& c) {
+    const float r = v * c.inv_vmax;
+    const int e = (int)__umul24((uint32_t)c.lshift, L);
+    float f;
+    if (c.clamp_mode == 0) {
+        const float g = ldexpf(r, e);
+        f = c.exp_is_one ? g : powf(g, c.p);
+        f = fmaxf(f, c.fmin);
+    } else {
+        const float g = ldexpf(fmaxf(r, c.fmin), e);
+        f = c.exp_is_one ? g : powf(g, c.p);
+    }
+    return f;
+}
+
+// Field count of a job: the variants MT = 1, 2, 4, 8 run batches whose jobs
+// all have exactly MT fields (a compile-time count); MT = 16 reads it per job.
+// Eq. 3 for P = 1 with the minimum importance on f (the paper's setting):
+// the same operations as importance_from_v takes for it
+__device__ __forceinline__ float importance_p1(float v, uint32_t L, const ImpCtx& c) {
+    const float r = v * c.inv_vmax;
+    const int e = (int)__umul24((uint32_t)c.lshift, L);
+    return fmaxf(ldexpf(r, e), c.fmin);
+}
+
+template <int MT>
+__device__ __forceinline__ int fields_of(int M) {
+    return MT <= 8 ? MT : M;
+}
+
+// A wave's streams over one run of a job: scalar base pointers advanced to
+// the run's first cell, so every load is a scalar base plus a 32-bit lane
+// offset (a run holds at most 1/64 of a volume, well below 2^32 bytes).
+template <int MT>
+struct RunView {
+    const char* base[MT];
+    const char* lev;
+};
+
+// values of the 4 cells of this lane in the given step
+template <int MT, typename S>
+struct StepData {
+    static constexpr uint32_t kQuadBytes = Quad<S>::kBytes;
+    Quad<S> q[MT];
+    uint32_t lv;
+    __device__ __forceinline__ void load(const JobDev& j, int M, int64_t quad) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            if (m < M) q[m].load(j.fields[m], quad);
+        lv = gload<uint32_t>(j.level, quad);
+    }
+    __device__ static const void* source(const JobDev& j, int m) { return j.fields[m]; }
+    // qd: quad index from the run's first cell
+    __device__ __forceinline__ void load(const RunView<MT>& v, int M, uint32_t qd) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            if (m < M) q[m].load_at(v.base[m], qd * kQuadBytes);
+        lv = gload_at<uint32_t>(v.lev, qd * 4u);
+    }
+};
+
+// TF entries of the 4 cells of this lane in the given step, from the
+// volume's entry cache (one byte per cell and field)
+template <int MT>
+struct StepIdx {
+    static constexpr uint32_t kQuadBytes = 4;
+    uint32_t e[MT];
+    uint32_t lv;
+    __device__ static const void* source(const JobDev& j, int m) { return j.idx[m]; }
+    __device__ __forceinline__ void load(const RunView<MT>& v, int M, uint32_t qd) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            if (m < M) e[m] = gload_at<uint32_t>(v.base[m], qd * 4u);
+        lv = gload_at<uint32_t>(v.lev, qd * 4u);
+    }
+};
+
+template <int MT, typename D>
+__device__ __forceinline__ RunView<MT> run_view(const JobDev& j, int M, int64_t c_begin) {
+    RunView<MT> v;
+    const int64_t quad0 = c_begin >> 2;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+        v.base[m] = m < M ? uni(reinterpret_cast<const char*>(D::source(j, m))) + quad0 * D::kQuadBytes : nullptr;
+    v.lev = uni(reinterpret_cast<const char*>(j.level)) + quad0 * 4;
+    return v;
+}
+
+// V of cell k of this lane for request q, from values or from cached
+// entries; off[m]: start of field m's table in `tf` (the request's block)
+template <int MT, typename S>
+__device__ __forceinline__ float cell_v(const StepData<MT, S>& d, int k, int M, const float* tf, const ReqDev& q,
+                                        const int (&off)[MT]) {
+    float xk[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) xk[m] = m < M ? d.q[m].get(k) : 0.0f;
+    return variation<MT>(xk, M, tf, q);
+}
+template <int MT>
+__device__ __forceinline__ float cell_v(const StepIdx<MT>& d, int k, int M, const float* tf, const ReqDev& q,
+                                        const int (&off)[MT]) {
+    float amax = -INFINITY, amin = INFINITY;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        if (m < M) {
+            const float al = tf[m * kIdxTable + (int)((d.e[m] >> (8 * k)) & 0xFFu)];
+            amax = fmaxf(amax, al);
+            amin = fminf(amin, al);
+        }
+    }
+    return amax - amin;
+}
+
+// the start of request q's tables in LDS for step type D
+template <int MT, typename D> struct TableBase {
+    __device__ static int of(int q, int toff) { return toff; }
+};
+template <int MT> struct TableBase<MT, StepIdx<MT>> {
+    __device__ static int of(int q, int toff) { return q * MT * kIdxTable; }
+};
+
+// a request's table offsets, in scalar registers
+template <int MT>
+__device__ __forceinline__ void table_offsets(const ReqDev& q, int M, int (&off)[MT]) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) off[m] = m < M ? uni(q.tf_off[m]) : 0;
+}
+
+// How many steps one loop iteration loads ahead: one 4-vector per field is
+// enough to keep HBM busy; cached entries are a quarter of that, so four
+// steps go together (tiles hold a multiple of four steps and are padded, so
+// the loads of a group stay inside the volume's buffers).
+template <typename D> struct Group { static constexpr int n = 1; };
+template <int MT> struct Group<StepIdx<MT>> { static constexpr int n = 4; };
+
+// ------------------------------------------------------------------ K0
+
+template <int MT, int KR, typename D>
+__device__ __forceinline__ void vmax_run(const BatchDev& b, const JobDev& j, int64_t r, const float* tf_lds) {
+    constexpr int G = Group<D>::n;
+    const int lane = lane_id();
+    const int M = uni(fields_of<MT>(j.M));
+    const int64_t n = uni(j.n);
+    const int64_t tile_cells = (int64_t)uni(j.tile_steps) * kStepCells;
+    const int64_t c_begin = r * uni(j.tiles_per_run) * tile_cells;
+    const int64_t c_end = min(n, (r + 1) * uni(j.tiles_per_run) * tile_cells);
+    const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
+    const ReqDev* rq = b.reqs + uni(j.req0);
+    float vmax[KR];
+    int toff[KR], off[KR][MT];
+#pragma unroll
+    for (int q = 0; q < KR; ++q) {
+        vmax[q] = 0.0f;
+        if (q < j.n_req) {
+            toff[q] = uni(rq[q].tf_job_off);
+            table_offsets<MT>(rq[q], M, off[q]);
+        }
+    }
+    const RunView<MT> view = run_view<MT, D>(j, M, c_begin);
+    for (int s = 0; s < nsteps; s += G) {
+        D d[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) d[g].load(view, M, (uint32_t)((s + g) * kWave + lane));
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (s + g >= nsteps) break;
+            const int64_t quad = ((c_begin + (int64_t)(s + g) * kStepCells) >> 2) + lane;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((quad << 2) + k >= n) continue;
+#pragma unroll
+                for (int q = 0; q < KR; ++q)
+                    if (q < j.n_req && rq[q].vmax_exact)
+                        vmax[q] = fmaxf(vmax[q], cell_v<MT>(d[g], k, M, tf_lds + TableBase<MT, D>::of(q, toff[q]), rq[q], off[q]));
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < KR; ++q) {
+        if (q < j.n_req && rq[q].vmax_exact) {
+            const float v = wave_max_f(vmax[q]);
+            if (lane == 0 && v > 0.0f) atomicMax(reinterpret_cast<unsigned int*>(rq[q].vmax_dev), __float_as_uint(v));
+        }
+    }
+}
+
+// Jobs that read values keep the requests' blocks as uploaded; jobs that read
+// cached entries (tables of <= 256 entries) place table (request q, field m)
+// at (q * MT + m) * 256 floats, so that every lookup address is the entry
+// times 4 plus a compile-time offset.
+template <int MT, bool IDX>
+__device__ __forceinline__ void load_job_tables(const BatchDev& b, const JobDev& j, int ji, int& loaded,
+                                                float* tf_lds) {
+    if (ji != loaded) {
+        __syncthreads();
+        if constexpr (IDX) {
+            const int M = uni(fields_of<MT>(j.M)), nq = uni(j.n_req);
+            const ReqDev* rq = b.reqs + uni(j.req0);
+            for (int i = threadIdx.x; i < nq * MT * kIdxTable; i += blockDim.x) {
+                const int q = i / (MT * kIdxTable), m = (i / kIdxTable) % MT, e = i % kIdxTable;
+                float v = 0.0f;
+                if (m < M && e < (int)rq[q].nmax[m] + 1) v = gload<float>(rq[q].tf, rq[q].tf_off[m] + e);
+                tf_lds[i] = v;
+            }
+        } else {
+            for (int i = threadIdx.x; i < j.tf_total_all; i += blockDim.x) tf_lds[i] = gload<float>(j.tf_all, i);
+        }
+        __syncthreads();
+        loaded = ji;
+    }
+}
+
+// IDX: this instance serves the jobs that read cached entries (1) or values (0)
+template <int MT, typename S, int KR, int IDX>
+__global__ __launch_bounds__(kUpdThreads) void k_vmax_exact(BatchDev b) {
+    extern __shared__ float tf_lds[];
+    const int wv = uni((int)(threadIdx.x / kWave));
+    int loaded = -1;
+    for (int64_t u = blockIdx.x; u < b.k1_units; u += gridDim.x) {
+        const int ji = find_job_k1(b, u);
+        const JobDev& j = b.jobs[ji];
+        if ((j.idx[0] != nullptr) != (IDX != 0)) continue;
+        load_job_tables<MT, IDX != 0>(b, j, ji, loaded, tf_lds);
+        const int64_t r = uni((u - j.k1_unit0) * (kUpdThreads / kWave) + wv);
+        if (r >= j.n_runs) continue;
+        if constexpr (IDX != 0)
+            vmax_run<MT, KR, StepIdx<MT>>(b, j, r, tf_lds);
+        else
+            vmax_run<MT, KR, StepData<MT, S>>(b, j, r, tf_lds);
+    }
+}
+
+// ------------------------------------------------------------------ K1
+
+// running sum of tile sums along a run, in the arithmetic of the scan mode
+struct RunAcc {
+    double d;
+    float hi, lo;
+    __device__ void init() { d = 0.0; hi = 0.0f; lo = 0.0f; }
+    __device__ double value(int mode) const {
+        return mode == DVL_SCAN_FP64 ? d : (mode == DVL_SCAN_KAHAN_FP32 ? (double)hi + (double)lo : (double)hi);
+    }
+    __device__ void add(int mode, double x) {
+        if (mode == DVL_SCAN_FP64) {
+            d += x;
+        } else if (mode == DVL_SCAN_KAHAN_FP32) {
+            const float xf = (float)x;
+            const float s = hi + xf, bb = s - hi;
+            const float e = (hi - (s - bb)) + (xf - bb);
+            const float l = lo + e;
+            hi = s + l;
+            lo = l - (hi - s);
+        } else {
+            hi += (float)x;
+        }
+    }
+};
+
+// One wave's run r of job j: stream its cells once (values, or cached
+// entries), evaluate f for every request of the job, sum f over each tile in
+// fp64 (per lane, 4 cells per step as (f0 + f1) + (f2 + f3), then the wave)
+// and record, per request and tile, the non-decreasing sum of the earlier
+// tiles of the run.  Both sources give the same f bit for bit.
+template <int MT, int KR, typename D, bool P1>
+__device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j, int64_t r, const float* tf_lds) {
+    constexpr int G = Group<D>::n;
+    const int lane = lane_id();
+    const int M = uni(fields_of<MT>(j.M));
+    const int nreq = KR == 1 ? 1 : uni(j.n_req);
+    const ReqDev* rq = b.reqs + uni(j.req0);
+    const int tile_steps = uni(j.tile_steps);
+    const int64_t n = uni(j.n);
+    const int64_t tile_cells = (int64_t)tile_steps * kStepCells;
+    const int64_t t_begin = r * uni(j.tiles_per_run);
+    const int64_t t_end = min(uni(j.n_tiles), t_begin + uni(j.tiles_per_run));
+    const int64_t c_begin = t_begin * tile_cells;
+    const int64_t c_end = min(n, t_end * tile_cells);
+    const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
+
+    ImpCtx ctx[KR];
+    RunAcc run[KR];
+    double prev[KR], tacc[KR];
+    int toff[KR], off[KR][MT];
+#pragma unroll
+    for (int q = 0; q < KR; ++q) {
+        if (q < nreq) {
+            ctx[q] = make_ctx(rq[q]);
+            toff[q] = uni(rq[q].tf_job_off);
+            table_offsets<MT>(rq[q], M, off[q]);
+        }
+        run[q].init();
+        prev[q] = 0.0;
+        tacc[q] = 0.0;
+    }
+    int64_t t = t_begin;
+    int in_tile = 0;
+    const RunView<MT> view = run_view<MT, D>(j, M, c_begin);
+    D cur[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) cur[g].load(view, M, (uint32_t)(g * kWave + lane));
+    for (int s = 0; s < nsteps; s += G) {
+        // the next group, unconditionally (the last group reloads the last
+        // step): a conditional load would make the compiler wait for all
+        // outstanding loads before using the current group
+        D nxt[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) nxt[g].load(view, M, (uint32_t)(min(s + G + g, nsteps - 1) * kWave + lane));
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (s + g >= nsteps) break;
+            const int64_t quad = ((c_begin + (int64_t)(s + g) * kStepCells) >> 2) + lane;
+            const bool full = c_begin + (int64_t)(s + g + 1) * kStepCells <= n;   // no cell past the end
+#pragma unroll
+            for (int q = 0; q < KR; ++q) {
+                if (q < nreq) {
+                    float f[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float v = cell_v<MT>(cur[g], k, M, tf_lds + TableBase<MT, D>::of(q, toff[q]), rq[q], off[q]);
+                        const uint32_t L = (cur[g].lv >> (8 * k)) & 0xFFu;
+                        f[k] = P1 ? importance_p1(v, L, ctx[q]) : importance_from_v(v, L, ctx[q]);
+                    }
+                    if (!full) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) f[k] = ((quad << 2) + k < n) ? f[k] : 0.0f;
+                    }
+                    tacc[q] += (double)((f[0] + f[1]) + (f[2] + f[3]));
+                }
+            }
+            if (++in_tile == tile_steps || s + g + 1 == nsteps) {
+#pragma unroll
+                for (int q = 0; q < KR; ++q) {
+                    if (q < nreq) {
+                        const int mode = rq[q].scan_mode;
+                        const double ts = wave_sum_d(tacc[q]);
+                        tacc[q] = 0.0;
+                        prev[q] = fmax(prev[q], run[q].value(mode));
+                        if (lane == 0) gstore<double>(rq[q].ws.local_prefix, t, prev[q]);
+                        run[q].add(mode, ts);
+                    }
+                }
+                ++t;
+                in_tile = 0;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) cur[g] = nxt[g];
+    }
+#pragma unroll
+    for (int q = 0; q < KR; ++q)
+        if (q < nreq && lane == 0) gstore<double>(rq[q].ws.run_total, r, fmax(prev[q], run[q].value(rq[q].scan_mode)));
+}
+
+// A workgroup takes 4 consecutive runs of one job; wave r of the job owns the
+// tiles [r k, (r + 1) k).
+template <int MT, typename S, int KR, int IDX>
+__global__ __launch_bounds__(kUpdThreads) void k_tile_sums(BatchDev b) {
+    extern __shared__ float tf_lds[];
+    const int wv = uni((int)(threadIdx.x / kWave));
+    int loaded = -1;
+    for (int64_t u = blockIdx.x; u < b.k1_units; u += gridDim.x) {
+        const int ji = find_job_k1(b, u);
+        const JobDev& j = b.jobs[ji];
+        if ((j.idx[0] != nullptr) != (IDX != 0)) continue;
+        load_job_tables<MT, IDX != 0>(b, j, ji, loaded, tf_lds);
+        const int64_t r = uni((u - j.k1_unit0) * (kUpdThreads / kWave) + wv);
+        if (r >= j.n_runs) continue;
+        // P = 1 with the importance clamp in every request of the job: no pow
+        bool p1 = true;
+        for (int q = 0; q < (KR == 1 ? 1 : j.n_req); ++q) {
+            const ReqDev& rq = b.reqs[j.req0 + q];
+            p1 = p1 && rq.exp_is_one && rq.clamp_mode == 0;
+        }
+        p1 = uni((int)p1) != 0;
+        if constexpr (IDX != 0) {
+            if (p1)
+                tile_sums_run<MT, KR, StepIdx<MT>, true>(b, j, r, tf_lds);
+            else
+                tile_sums_run<MT, KR, StepIdx<MT>, false>(b, j, r, tf_lds);
+        } else {
+            if (p1)
+                tile_sums_run<MT, KR, StepData<MT, S>, true>(b, j, r, tf_lds);
+            else
+                tile_sums_run<MT, KR, StepData<MT, S>, false>(b, j, r, tf_lds);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ K3 helpers
+
+template <int MT>
+struct Seg {
+    double sum[MT];
+    float mn[MT];
+    float mx[MT];
+    uint32_t first;
+    uint32_t last;
+};
+
+template <int MT>
+__device__ __forceinline__ void seg_clear(Seg<MT>& s) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        s.sum[m] = 0.0;
+        s.mn[m] = INFINITY;
+        s.mx[m] = -INFINITY;
+    }
+    s.first = 0xFFFFFFFFu;
+    s.last = 0u;
+}
+
+// a precedes b in cell order
+template <int MT>
+__device__ __forceinline__ Seg<MT> seg_combine(const Seg<MT>& a, const Seg<MT>& b) {
+    Seg<MT> r;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        r.sum[m] = a.sum[m] + b.sum[m];
+        r.mn[m] = fminf(a.mn[m], b.mn[m]);
+        r.mx[m] = fmaxf(a.mx[m], b.mx[m]);
+    }
+    r.first = min(a.first, b.first);
+    r.last = max(a.last, b.last);
+    return r;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ o) << 2, (int)v));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ o) << 2, (int)v));
+    return v;
+}
+__device__ __forceinline__ int wave_min_i32(int v) {
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, __builtin_amdgcn_ds_bpermute((lane_id() ^ o) << 2, v));
+    return v;
+}
+
+// Sum of the importance of all tiles before tile t (t = T gives F_tot): the
+// run's base plus the tile's prefix inside its run, never above the next
+// run's base.  One definition serves both neighbours of every tile boundary,
+// and the offsets never decrease.
+__device__ __forceinline__ double tile_offset(const JobDev& j, const UpdWorkspace& ws, int64_t t,
+                                              bool degenerate) {
+    const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
+    if (degenerate) return t >= j.n_tiles ? (double)j.n : (double)(t * tile_cells);
+    if (t >= j.n_tiles) return gload<double>(ws.run_base, j.n_runs);
+    const int64_t r = t / j.tiles_per_run;
+    const double lo = gload<double>(ws.run_base, r), hi = gload<double>(ws.run_base, r + 1);
+    return fmin(fmax(lo + gload<double>(ws.local_prefix, t), lo), hi);
+}
+
+// LDS scratch of the bin reductions of one wave: the partial statistics of up
+// to kRedFields fields for the 64 lanes, then the reduced values.
+constexpr int kRedFields = 4;
+struct RedScratch {
+    double sum[kRedFields][kWave];
+    float mn[kRedFields][kWave];
+    float mx[kRedFields][kWave];
+    double rsum[kRedFields];
+    float rmn[kRedFields];
+    float rmx[kRedFields];
+};
+constexpr size_t kRedBytes = sizeof(RedScratch);
+
+// Reduce the per-lane partials (asum, amin, amax) of one bin over the wave
+// and store the bin: a complete bin (dest 0) gets its final mean, min, max
+// and height; a tile-edge bin goes to the tile's head (dest 1) or tail
+// (dest 2) record.  Fields are taken kRedFields at a time; lane j < F reduces
+// the sums of field j in lane order, lanes 16 + j and 32 + j its minima and
+// maxima, and lanes m < F finalise field m.
+template <int MT>
+__device__ void close_bin(const ReqDev& q, int M, int64_t T, RedScratch* rs, int dest, int64_t t, int key,
+                          uint32_t first, uint32_t last, const double (&asum)[MT],
+                          const float (&amin)[MT], const float (&amax)[MT], const float* tf) {
+    const int lane = lane_id();
+    const uint32_t cnt = last - first + 1u;
+#pragma unroll
+    for (int m0 = 0; m0 < MT; m0 += kRedFields) {
+        if (m0 >= M) break;
+#pragma unroll
+        for (int jj = 0; jj < kRedFields; ++jj) {
+            if (m0 + jj < MT) {
+                rs->sum[jj][lane] = asum[m0 + jj];
+                rs->mn[jj][lane] = amin[m0 + jj];
+                rs->mx[jj][lane] = amax[m0 + jj];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int nf = min(kRedFields, M - m0);
+        if (lane < nf) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            for (int l = 0; l < kWave; l += 4) {
+                s0 += rs->sum[lane][l];
+                s1 += rs->sum[lane][l + 1];
+                s2 += rs->sum[lane][l + 2];
+                s3 += rs->sum[lane][l + 3];
+            }
+            rs->rsum[lane] = (s0 + s1) + (s2 + s3);
+        } else if (lane >= 16 && lane < 16 + nf) {
+            const int jj = lane - 16;
+            float v = INFINITY;
+            for (int l = 0; l < kWave; ++l) v = fminf(v, rs->mn[jj][l]);
+            rs->rmn[jj] = v;
+        } else if (lane >= 32 && lane < 32 + nf) {
+            const int jj = lane - 32;
+            float v = -INFINITY;
+            for (int l = 0; l < kWave; ++l) v = fmaxf(v, rs->mx[jj][l]);
+            rs->rmx[jj] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < nf) {
+            const int m = m0 + lane;
+            const double sm = rs->rsum[lane];
+            const float mn = rs->rmn[lane], mx = rs->rmx[lane];
+            if (dest == 0) {
+                const float mean = (float)(sm / (double)cnt);
+                const int e = tf_entry(mean, q.s[m], q.b[m], q.nmax[m]);
+                const int64_t o = (int64_t)m * q.W + key;
+                gstore<float>(q.mean, o, mean);
+                gstore<float>(q.vmin, o, mn);
+                gstore<float>(q.vmax, o, mx);
+                gstore<float>(q.y, o, tf[q.tf_off[m] + e]);
+            } else {
+                const int64_t o = ((int64_t)(dest - 1) * M + m) * T + t;
+                gstore<double>(q.ws.rec_sum, o, sm);
+                gstore<float>(q.ws.rec_min, o, mn);
+                gstore<float>(q.ws.rec_max, o, mx);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0) {
+        if (dest == 0) {
+            gstore<uint32_t>(q.first_cell, key, first);
+            gstore<uint32_t>(q.last_cell, key, last);
+        } else {
+            gstore<uint32_t>(q.ws.rec_first, (dest - 1) * T + t, first);
+            gstore<uint32_t>(q.ws.rec_last, (dest - 1) * T + t, last);
+        }
+    }
+}
+
+// a bin that holds one cell only (strictly inside a wide cell)
+template <int MT>
+__device__ void write_single(const ReqDev& q, int M, int key, const float (&x)[MT], uint32_t g, const float* tf) {
+    gstore<uint32_t>(q.first_cell, key, g);
+    gstore<uint32_t>(q.last_cell, key, g);
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        if (m < M) {
+            const int e = tf_entry(x[m], q.s[m], q.b[m], q.nmax[m]);
+            const int64_t o = (int64_t)m * q.W + key;
+            gstore<float>(q.mean, o, x[m]);
+            gstore<float>(q.vmin, o, x[m]);
+            gstore<float>(q.vmax, o, x[m]);
+            gstore<float>(q.y, o, tf[q.tf_off[m] + e]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ K3
+
+constexpr int kBinThreads = 64;   // one wave per workgroup: each unit is one (request, tile)
+
+// Pixel interval [X0, X1] of tile t of request q, and its first and last bin.
+struct TileSpan {
+    double scale_d;
+    float scale_f, X0, X1;
+    int b0, b1;
+};
+
+__device__ __forceinline__ TileSpan tile_span(const ReqDev& q, const JobDev& j, int64_t t) {
+    TileSpan sp;
+    const bool degenerate = gload<double>(q.ws.scal, 1) != 0.0;
+    sp.scale_d = (double)q.W / gload<double>(q.ws.scal, 0);
+    sp.scale_f = (float)sp.scale_d;
+    sp.X0 = (float)(tile_offset(j, q.ws, t, degenerate) * sp.scale_d);
+    sp.X1 = (float)(tile_offset(j, q.ws, t + 1, degenerate) * sp.scale_d);
+    const int W1 = q.W - 1;
+    sp.b0 = max(0, min((int)floorf(sp.X0), W1));
+    sp.b1 = max(0, min((int)floorf(sp.X1), W1));
+    return sp;
+}
+
+// K3b: the queued tiles, one wave each.
+template <int MT, typename S>
+__global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
+    extern __shared__ float lds[];
+    RedScratch* rs = reinterpret_cast<RedScratch*>(lds);
+    float* tf_lds = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + (kRedBytes + 15) / 16 * 16);
+    const int lane = lane_id();
+    int loaded = -1;
+    const int64_t n_queued = gload<uint32_t>(bd.rescan_count, 0);
+
+    for (int64_t i = blockIdx.x; i < n_queued; i += gridDim.x) {
+        const int64_t u = uni((int64_t)gload<uint64_t>(bd.rescan_queue, i));
+        const int qi = uni(find_req_k3(bd, u));
+        const ReqDev& q = bd.reqs[qi];
+        const JobDev& j = bd.jobs[uni(q.job)];
+        const int64_t t = u - uni(q.k3_unit0);
+        const int M = uni(fields_of<MT>(j.M));
+        const int64_t T = uni(j.n_tiles);
+        const int64_t n = uni(j.n);
+        const bool degenerate = uni((int)(gload<double>(q.ws.scal, 1) != 0.0)) != 0;
+        const TileSpan sp = tile_span(q, j, t);
+        const float scale_f = uni(sp.scale_f), X0 = uni(sp.X0), X1 = uni(sp.X1);
+        const int W1 = uni(q.W) - 1;
+        const int64_t tile_cells = (int64_t)uni(j.tile_steps) * kStepCells;
+        const int64_t tbase = t * tile_cells;
+        const int64_t tend = min(tbase + tile_cells, n);
+        const uint32_t last_valid = (uint32_t)(tend - 1);
+        const int nsteps = (int)((tend - tbase + kStepCells - 1) / kStepCells);
+        const RunView<MT> view = run_view<MT, StepData<MT, S>>(j, M, tbase);
+
+        // the tile is rescanned: this request's tables in LDS
+        if (qi != loaded) {
+            __builtin_amdgcn_wave_barrier();
+            for (int i = lane; i < q.tf_total; i += kWave) tf_lds[i] = gload<float>(q.tf, i);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            loaded = qi;
+        }
+        const ImpCtx c = make_ctx(q);
+
+        float run = 0.0f;
+        bool o_valid = false;
+        int O = -1, Bh = -1;
+        uint32_t O_first = 0, O_last = 0;
+        double asum[MT];
+        float amin[MT], amax[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            asum[m] = 0.0;
+            amin[m] = INFINITY;
+            amax[m] = -INFINITY;
+        }
+
+        StepData<MT, S> cur, nx1;
+        cur.load(view, M, (uint32_t)lane);
+        nx1.load(view, M, (uint32_t)(min(1, nsteps - 1) * kWave + lane));
+        for (int s = 0; s < nsteps; ++s) {
+            const int64_t c0 = tbase + (int64_t)s * kStepCells;
+            const int64_t quad = (c0 >> 2) + lane;
+            StepData<MT, S> nxt;
+            nxt.load(view, M, (uint32_t)(min(s + 2, nsteps - 1) * kWave + lane));
+
+            float x[MT][4];
+            float f[4];
+            uint32_t g[4];
+            bool valid[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float xk[MT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    xk[m] = m < M ? cur.q[m].get(k) : 0.0f;
+                    x[m][k] = xk[m];
+                }
+                g[k] = (uint32_t)((quad << 2) + k);
+                valid[k] = (int64_t)g[k] < n;
+                float fk = 1.0f;
+                if (!degenerate) fk = importance_from_v(variation<MT>(xk, M, tf_lds, q),
+                                                        (cur.lv >> (8 * k)) & 0xFFu, c);
+                f[k] = valid[k] ? fk : 0.0f;
+            }
+
+            // monotone in-tile prefix: lane-serial over 4 cells, wave sum scan,
+            // running max to undo rounding steps back, min-clamp inside the lane
+            const float p1 = f[0], p2 = p1 + f[1], p3 = p2 + f[2], tl = p3 + f[3];
+            const float B = wave_incl_max(wave_incl_sum(tl));
+            const float Bex = shfl_up1(B, 0.0f);
+            const float stot = readlane(B, kWave - 1);
+            float xs[5];
+            xs[0] = fminf(fmaf(run + fminf(Bex, B), scale_f, X0), X1);
+            xs[1] = fminf(fmaf(run + fminf(Bex + p1, B), scale_f, X0), X1);
+            xs[2] = fminf(fmaf(run + fminf(Bex + p2, B), scale_f, X0), X1);
+            xs[3] = fminf(fmaf(run + fminf(Bex + p3, B), scale_f, X0), X1);
+            xs[4] = fminf(fmaf(run + B, scale_f, X0), X1);
+            run = run + stot;
+
+            // pixel bins of each cell: [floor(x1), ceil(x2) - 1], clamped
+            int blo[4], bhi[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float en = (g[k] == last_valid) ? X1 : xs[k + 1];
+                blo[k] = max(0, min((int)floorf(xs[k]), W1));
+                bhi[k] = max(blo[k], min((int)ceilf(en) - 1, W1));
+            }
+
+            const bool full = c0 + kStepCells <= n;
+            const int key0 = readlane(blo[0], 0);
+            if (s == 0) Bh = key0;
+            const int key_end = full ? readlane(bhi[3], kWave - 1) : INT_MAX;
+
+            if (full && key0 == key_end && (!o_valid || key0 == O)) {
+                // the whole step lies in one bin: per-lane accumulation
+                if (!o_valid) {
+                    o_valid = true;
+                    O = key0;
+                    O_first = (uint32_t)c0;
+                }
+                O_last = (uint32_t)(c0 + kStepCells - 1);
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    if (m < M) {
+                        const float s4 = (x[m][0] + x[m][1]) + (x[m][2] + x[m][3]);
+                        asum[m] += (double)s4;
+                        amin[m] = fminf(amin[m], fminf(fminf(x[m][0], x[m][1]), fminf(x[m][2], x[m][3])));
+                        amax[m] = fmaxf(amax[m], fmaxf(fmaxf(x[m][0], x[m][1]), fmaxf(x[m][2], x[m][3])));
+                    }
+                }
+                cur = nx1;
+                nx1 = nxt;
+                continue;
+            }
+
+            // ---- bin boundary inside the step ----
+            const int last_lane = full ? kWave - 1 : (int)((n - 1 - c0) >> 2);
+            const int kl = (int)((n - 1 - c0) & 3);
+            const int bhi_last = kl == 0 ? bhi[0] : (kl == 1 ? bhi[1] : (kl == 2 ? bhi[2] : bhi[3]));
+            const int key_last = full ? key_end : readlane(bhi_last, last_lane);
+            // (1) the open bin ended with the previous step: reduce and emit it
+            if (o_valid && key0 != O) {
+                close_bin<MT>(q, M, T, rs, O == Bh ? 1 : 0, t, O, O_first, O_last, asum, amin, amax, tf_lds);
+                o_valid = false;
+            }
+            // (2) bins strictly inside a wide cell hold that cell alone
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (valid[k] && bhi[k] > blo[k] + 1) {
+                    float xk[MT];
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) xk[m] = x[m][k];
+                    for (int bb = blo[k] + 1; bb < bhi[k]; ++bb) write_single<MT>(q, M, bb, xk, g[k], tf_lds);
+                }
+            }
+            // (3) every bin that is the first or last bin of some cell of this
+            //     step, in increasing order; all but the step's last one close
+            int b = key0;
+            while (true) {
+                bool in[4];
+                uint32_t gmin = 0xFFFFFFFFu, gmax = 0u;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    in[k] = valid[k] && (blo[k] == b || bhi[k] == b);
+                    if (in[k]) {
+                        gmin = min(gmin, g[k]);
+                        gmax = max(gmax, g[k]);
+                    }
+                }
+                const bool cont = o_valid && b == O;   // continues the open bin
+                if (!cont) {
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+                        asum[m] = 0.0;
+                        amin[m] = INFINITY;
+                        amax[m] = -INFINITY;
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    if (m < M) {
+                        float s4 = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (in[k]) {
+                                s4 += x[m][k];
+                                amin[m] = fminf(amin[m], x[m][k]);
+                                amax[m] = fmaxf(amax[m], x[m][k]);
+                            }
+                        }
+                        asum[m] += (double)s4;
+                    }
+                }
+                const uint32_t bfirst = cont ? O_first : wave_min_u32(gmin);
+                if (b == key_last) {
+                    // stays open into the next step (per-lane accumulators keep it)
+                    O = b;
+                    O_first = bfirst;
+                    O_last = (uint32_t)min((int64_t)c0 + kStepCells - 1, n - 1);
+                    o_valid = true;
+                    break;
+                }
+                close_bin<MT>(q, M, T, rs, b == Bh ? 1 : 0, t, b, bfirst, wave_max_u32(gmax), asum, amin, amax,
+                              tf_lds);
+                o_valid = false;
+                int nk = INT_MAX;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (valid[k]) {
+                        if (blo[k] > b) nk = min(nk, blo[k]);
+                        if (bhi[k] > b) nk = min(nk, bhi[k]);
+                    }
+                }
+                b = wave_min_i32(nk);
+                if (b == INT_MAX) break;   // cannot happen: key_last is above
+            }
+            cur = nx1;
+            nx1 = nxt;
+        }
+
+        // tile end: the open bin is the tile's last bin
+        if (o_valid) {
+            close_bin<MT>(q, M, T, rs, O == Bh ? 1 : 2, t, O, O_first, O_last, asum, amin, amax, tf_lds);
+            if (lane == 0) {
+                gstore<int32_t>(q.ws.head_bin, t, Bh);
+                gstore<int32_t>(q.ws.tail_bin, t, O);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launcher
+
+// launchers of the kernels that do not depend on the storage type (update.hip)
+dvl_status launch_carry(const BatchDev& b, hipStream_t s);
+dvl_status launch_classify(const BatchDev& b, hipStream_t s);
+dvl_status launch_edges(const BatchDev& b, int mt, hipStream_t s);
+
+template <int MT, typename S, int KR>
+static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEvent_t* ev) {
+    auto mark = [&](int i) -> dvl_status {
+        if (ev) DVL_HIP(hipEventRecord(ev[i], s));
+        return DVL_OK;
+    };
+    const size_t lds1 = (size_t)b.max_job_tf * sizeof(float);
+    const size_t lds1i = (size_t)std::max(1, b.max_req_job) * MT * kIdxTable * sizeof(float);
+    const unsigned g1 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.k1_units, (int64_t)n_cu * 8));
+    if (dvl_status st = mark(0)) return st;
+    if (b.any_exact) {
+        if (b.paths & kPathValues) {
+            hipLaunchKernelGGL((k_vmax_exact<MT, S, KR, 0>), dim3(g1), dim3(kUpdThreads), lds1, s, b);
+            DVL_HIP(hipGetLastError());
+        }
+        if (b.paths & kPathEntries) {
+            hipLaunchKernelGGL((k_vmax_exact<MT, S, KR, 1>), dim3(g1), dim3(kUpdThreads), lds1i, s, b);
+            DVL_HIP(hipGetLastError());
+        }
+    }
+    if (dvl_status st = mark(1)) return st;
+    if (b.paths & kPathValues) {
+        hipLaunchKernelGGL((k_tile_sums<MT, S, KR, 0>), dim3(g1), dim3(kUpdThreads), lds1, s, b);
+        DVL_HIP(hipGetLastError());
+    }
+    if (b.paths & kPathEntries) {
+        hipLaunchKernelGGL((k_tile_sums<MT, S, KR, 1>), dim3(g1), dim3(kUpdThreads), lds1i, s, b);
+        DVL_HIP(hipGetLastError());
+    }
+    if (dvl_status st = mark(2)) return st;
+    if (dvl_status st = launch_carry(b, s)) return st;
+    if (dvl_status st = mark(3)) return st;
+    if (dvl_status st = launch_classify(b, s)) return st;
+    const size_t lds3 = (kRedBytes + 15) / 16 * 16 + (size_t)b.max_req_tf * sizeof(float);
+    const unsigned g3 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.k3_units, (int64_t)n_cu * 16));
+    hipLaunchKernelGGL((k_bin<MT, S>), dim3(g3), dim3(kBinThreads), lds3, s, b);
+    DVL_HIP(hipGetLastError());
+    if (dvl_status st = mark(4)) return st;
+    if (dvl_status st = launch_edges(b, MT, s)) return st;
+    return mark(5);
+}
+
+// Field-count variants: batches whose jobs all have 1, 2, 4 or 8 fields run
+// the variant with that count fixed at compile time; others (mixed counts,
+// 3, 5-7 or more than 8 fields) the general variant, which reads M per job.
+template <typename S, int KR>
+static dvl_status launch_m(const BatchDev& b, int max_m, int n_cu, hipStream_t s, hipEvent_t* ev) {
+    switch (max_m) {
+        case 1: return launch_typed<1, S, KR>(b, n_cu, s, ev);
+        case 2: return launch_typed<2, S, KR>(b, n_cu, s, ev);
+        case 4: return launch_typed<4, S, KR>(b, n_cu, s, ev);
+        case 8: return launch_typed<8, S, KR>(b, n_cu, s, ev);
+        default: return launch_typed<16, S, KR>(b, n_cu, s, ev);
+    }
+}
+
+template <typename S>
+static dvl_status launch_s(const BatchDev& b, int max_m, int max_req, int n_cu, hipStream_t s, hipEvent_t* ev) {
+    if (max_req <= 1) return launch_m<S, 1>(b, max_m, n_cu, s, ev);
+    return launch_m<S, kMaxReqPerJob>(b, max_m, n_cu, s, ev);
+}
+
+// one per storage type, each in its own translation unit (update_<type>.hip)
+dvl_status launch_batch_f32(const BatchDev& b, int max_m, int max_req, int n_cu, hipStream_t s, hipEvent_t* ev);
+dvl_status launch_batch_f16(const BatchDev& b, int max_m, int max_req, int n_cu, hipStream_t s, hipEvent_t* ev);
+dvl_status launch_batch_bf16(const BatchDev& b, int max_m, int max_req, int n_cu, hipStream_t s, hipEvent_t* ev);
+
+}  // namespace dvl
