@@ -112,10 +112,14 @@ struct dvl_volume {
     uint32_t* perm = nullptr;
     float dmin[kMaxFields] = {};
     float dmax[kMaxFields] = {};
-    // per-tile statistics of the sorted fields: sum [M][T], min [M][T], max [M][T]
+    // per-tile statistics of the sorted fields: sum [M][T], min [M][T], max [M][T],
+    // and per 256-cell step: [M][S], S = T * tile_steps
     double* agg_sum = nullptr;
     float* agg_min = nullptr;
     float* agg_max = nullptr;
+    double* step_sum = nullptr;
+    float* step_min = nullptr;
+    float* step_max = nullptr;
     // TF entry cache: one byte per sorted cell and field for one CacheKey
     // (policy DVL_ENTRY_CACHE_*); `cand` is the key of the last update that
     // could have used a cache, so a key seen twice in a row gets one
@@ -374,6 +378,9 @@ static dvl_status plan_batch(std::vector<ReqHost>&& reqs, Plan& P) {
         j.agg_sum = v->agg_sum;
         j.agg_min = v->agg_min;
         j.agg_max = v->agg_max;
+        j.step_sum = v->step_sum;
+        j.step_min = v->step_min;
+        j.step_max = v->step_max;
         int tf_job = 0;
         size_t k = i;
         while (k < P.reqs.size() && P.reqs[k].v == v && (int)(k - i) < kMaxReqPerJob &&
@@ -790,6 +797,14 @@ struct dvl_graph {
     }
 };
 
+// per-tile and per-step statistics of sorted field m
+static dvl_status tile_aggregates(dvl_volume* v, int m, hipStream_t s) {
+    const size_t ot = (size_t)m * v->n_tiles, os = ot * v->tile_steps;
+    return launch_tile_aggregates(v->n, v->dtype, v->fields_s[m], v->n_tiles, v->tile_steps, v->agg_sum + ot,
+                                  v->agg_min + ot, v->agg_max + ot, v->step_sum + os, v->step_min + os,
+                                  v->step_max + os, v->n_cu, s);
+}
+
 extern "C" {
 
 const char* dvl_last_error(void) { return g_err.c_str(); }
@@ -917,21 +932,24 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
         v->bytes += (size_t)v->n_pad * eb;
     }
     {
-        DevBuf as, an, ax;
+        DevBuf as, an, ax, ss, sn, sx;
         const size_t mt = (size_t)M * v->n_tiles;
+        const size_t ms = mt * v->tile_steps;
         if (dvl_status st = as.alloc(mt * 8, "tile sums")) return st;
         if (dvl_status st = an.alloc(mt * 4, "tile minima")) return st;
         if (dvl_status st = ax.alloc(mt * 4, "tile maxima")) return st;
+        if (dvl_status st = ss.alloc(ms * 8, "step sums")) return st;
+        if (dvl_status st = sn.alloc(ms * 4, "step minima")) return st;
+        if (dvl_status st = sx.alloc(ms * 4, "step maxima")) return st;
         v->agg_sum = (double*)as.release();
         v->agg_min = (float*)an.release();
         v->agg_max = (float*)ax.release();
-        v->bytes += mt * 16;
+        v->step_sum = (double*)ss.release();
+        v->step_min = (float*)sn.release();
+        v->step_max = (float*)sx.release();
+        v->bytes += (mt + ms) * 16;
         for (int m = 0; m < M; ++m)
-            if (dvl_status st = launch_tile_aggregates(n, dtype, v->fields_s[m], v->n_tiles, v->tile_steps,
-                                                       v->agg_sum + (size_t)m * v->n_tiles,
-                                                       v->agg_min + (size_t)m * v->n_tiles,
-                                                       v->agg_max + (size_t)m * v->n_tiles, v->n_cu, s))
-                return st;
+            if (dvl_status st = tile_aggregates(v, m, s)) return st;
     }
     DVL_HIP(hipMemcpyAsync(rinit.data(), rng.p, rinit.size() * 4, hipMemcpyDeviceToHost, s));
     DVL_HIP(hipStreamSynchronize(s));
@@ -970,10 +988,7 @@ dvl_status dvl_set_field(dvl_volume* v, int32_t m, const void* values, void* str
     DVL_HIP(hipMemcpyAsync(rng.p, r, sizeof r, hipMemcpyHostToDevice, s));
     if (dvl_status st = launch_gather(v->n, v->perm, values, v->fields_s[m], eb, s)) { v->sticky = st; return st; }
     if (dvl_status st = launch_range(v->n, v->dtype, v->fields_s[m], (unsigned int*)rng.p, s)) { v->sticky = st; return st; }
-    if (dvl_status st = launch_tile_aggregates(v->n, v->dtype, v->fields_s[m], v->n_tiles, v->tile_steps,
-                                               v->agg_sum + (size_t)m * v->n_tiles,
-                                               v->agg_min + (size_t)m * v->n_tiles,
-                                               v->agg_max + (size_t)m * v->n_tiles, v->n_cu, s)) {
+    if (dvl_status st = tile_aggregates(v, m, s)) {
         v->sticky = st;
         return st;
     }
@@ -1141,6 +1156,9 @@ void dvl_destroy(dvl_volume* v) {
     if (v->agg_sum) (void)hipFree(v->agg_sum);
     if (v->agg_min) (void)hipFree(v->agg_min);
     if (v->agg_max) (void)hipFree(v->agg_max);
+    if (v->step_sum) (void)hipFree(v->step_sum);
+    if (v->step_min) (void)hipFree(v->step_min);
+    if (v->step_max) (void)hipFree(v->step_max);
     for (int m = 0; m < kMaxFields; ++m)
         if (v->idx_s[m]) (void)hipFree(v->idx_s[m]);
     delete v;

@@ -361,13 +361,18 @@ __global__ __launch_bounds__(256) void k_edges(BatchDev bd) {
 
 // ------------------------------------------------------------------ per-tile statistics
 
-// sum / min / max of one sorted field over every tile; one wave per tile
-// (computed once per volume and per data change, not per update)
+// sum / min / max of one sorted field over every tile and over every 256-cell
+// step; one wave per tile (computed once per volume and per data change, not
+// per update).  Tile sums: per lane, fp32 sums of 4 values accumulated in fp64
+// over the steps, then the wave; step sums: per lane the fp64 sum of its 4
+// values, then the wave.
 template <typename S>
 __global__ __launch_bounds__(kUpdThreads) void k_tile_aggregates(int64_t n, const void* __restrict__ field,
                                                                  int64_t n_tiles, int tile_steps,
                                                                  double* __restrict__ sum,
-                                                                 float* __restrict__ mn, float* __restrict__ mx) {
+                                                                 float* __restrict__ mn, float* __restrict__ mx,
+                                                                 double* __restrict__ ssum,
+                                                                 float* __restrict__ smn, float* __restrict__ smx) {
     const int lane = lane_id();
     const int64_t wave = (int64_t)blockIdx.x * (kUpdThreads / kWave) + threadIdx.x / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * (kUpdThreads / kWave);
@@ -380,16 +385,30 @@ __global__ __launch_bounds__(kUpdThreads) void k_tile_aggregates(int64_t n, cons
             Quad<S> q;
             q.load(field, quad);
             float s4 = 0.0f;
+            double d4 = 0.0;
+            float slo = INFINITY, shi = -INFINITY;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if ((quad << 2) + k < n) {
                     const float v = q.get(k);
                     s4 += v;
-                    lo = fminf(lo, v);
-                    hi = fmaxf(hi, v);
+                    d4 += (double)v;
+                    slo = fminf(slo, v);
+                    shi = fmaxf(shi, v);
                 }
             }
             acc += (double)s4;
+            lo = fminf(lo, slo);
+            hi = fmaxf(hi, shi);
+            d4 = wave_sum_d(d4);
+            slo = wave_min_f(slo);
+            shi = wave_max_f(shi);
+            if (lane == 0) {
+                const int64_t gs = t * tile_steps + st;
+                ssum[gs] = d4;
+                smn[gs] = slo;
+                smx[gs] = shi;
+            }
         }
         acc = wave_sum_d(acc);
         lo = wave_min_f(lo);
@@ -403,18 +422,19 @@ __global__ __launch_bounds__(kUpdThreads) void k_tile_aggregates(int64_t n, cons
 }
 
 dvl_status launch_tile_aggregates(int64_t n, int dtype, const void* field, int64_t n_tiles, int tile_steps,
-                                  double* sum, float* mn, float* mx, int n_cu, hipStream_t s) {
+                                  double* sum, float* mn, float* mx, double* ssum, float* smn, float* smx,
+                                  int n_cu, hipStream_t s) {
     const int64_t wg_needed = (n_tiles + (kUpdThreads / kWave) - 1) / (kUpdThreads / kWave);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(wg_needed, (int64_t)n_cu * 8));
     if (dtype == DVL_F16)
         hipLaunchKernelGGL(k_tile_aggregates<F16>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles,
-                           tile_steps, sum, mn, mx);
+                           tile_steps, sum, mn, mx, ssum, smn, smx);
     else if (dtype == DVL_BF16)
         hipLaunchKernelGGL(k_tile_aggregates<BF16>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles,
-                           tile_steps, sum, mn, mx);
+                           tile_steps, sum, mn, mx, ssum, smn, smx);
     else
         hipLaunchKernelGGL(k_tile_aggregates<F32>, dim3(grid), dim3(kUpdThreads), 0, s, n, field, n_tiles,
-                           tile_steps, sum, mn, mx);
+                           tile_steps, sum, mn, mx, ssum, smn, smx);
     DVL_HIP(hipGetLastError());
     return DVL_OK;
 }

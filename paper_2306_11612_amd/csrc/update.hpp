@@ -90,6 +90,9 @@ struct JobDev {
     const double* agg_sum;    // per-tile field statistics [M][T]
     const float* agg_min;
     const float* agg_max;
+    const double* step_sum;   // per-step (256 cells) field statistics [M][T * tile_steps]
+    const float* step_min;
+    const float* step_max;
     const float* tf_all;      // the requests' tables, request after request
 };
 
@@ -121,8 +124,10 @@ dvl_status launch_batch(const BatchDev& b, int dtype, int max_m, int max_req, in
 dvl_status launch_build_index(int64_t n_pad, int dtype, const void* field, float s, float b, int n_tf,
                               uint8_t* out, int n_cu, hipStream_t st);
 
-// Per-tile sum / min / max of one sorted field.
+// Per-tile and per-step (256 cells) sum / min / max of one sorted field:
+// tile arrays [n_tiles], step arrays [n_tiles * tile_steps].
 dvl_status launch_tile_aggregates(int64_t n, int dtype, const void* field, int64_t n_tiles, int tile_steps,
-                                  double* sum, float* mn, float* mx, int n_cu, hipStream_t s);
+                                  double* sum, float* mn, float* mx, double* ssum, float* smn, float* smx,
+                                  int n_cu, hipStream_t s);
 
 }  // namespace dvl

@@ -545,89 +545,101 @@ __device__ __forceinline__ double tile_offset(const JobDev& j, const UpdWorkspac
     return fmin(fmax(lo + gload<double>(ws.local_prefix, t), lo), hi);
 }
 
-// LDS scratch of the bin reductions of one wave: the partial statistics of up
-// to kRedFields fields for the 64 lanes, then the reduced values.
-constexpr int kRedFields = 4;
-struct RedScratch {
-    double sum[kRedFields][kWave];
-    float mn[kRedFields][kWave];
-    float mx[kRedFields][kWave];
-    double rsum[kRedFields];
-    float rmn[kRedFields];
-    float rmx[kRedFields];
-};
-constexpr size_t kRedBytes = sizeof(RedScratch);
+// Field statistics of the sorted cells [first, last] of one tile (tbase: its
+// first cell; view: its streams), computed by the whole wave from the stored
+// values of the partial 256-cell steps at both ends and the per-step
+// statistics of the steps in between (at most tile_steps - 2 < 64 of them,
+// one per lane).  Sums are fp64; every lane ends with the result.
+template <int MT, typename S>
+__device__ __forceinline__ void range_stats(const JobDev& j, int M, const RunView<MT>& view, int64_t tbase,
+                                            int64_t step0, uint32_t first, uint32_t last, double (&sum)[MT],
+                                            float (&mn)[MT], float (&mx)[MT]) {
+    const int lane = lane_id();
+    const int sf = (int)(((int64_t)first - tbase) >> 8), sl = (int)(((int64_t)last - tbase) >> 8);
+    const int64_t S_all = (int64_t)uni(j.n_tiles) * uni(j.tile_steps);
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        sum[m] = 0.0;
+        mn[m] = INFINITY;
+        mx[m] = -INFINITY;
+    }
+    // the lane's 4 cells of the first step, then of the last step
+#pragma unroll
+    for (int end = 0; end < 2; ++end) {
+        if (end == 1 && sl == sf) break;
+        const int st = end == 0 ? sf : sl;
+        const int64_t c = tbase + (int64_t)st * kStepCells + 4 * lane;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            if (m < M) {
+                Quad<S> qd;
+                qd.load_at(view.base[m], (uint32_t)(st * kWave + lane) * Quad<S>::kBytes);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (c + k >= (int64_t)first && c + k <= (int64_t)last) {
+                        const float v = qd.get(k);
+                        sum[m] += (double)v;
+                        mn[m] = fminf(mn[m], v);
+                        mx[m] = fmaxf(mx[m], v);
+                    }
+                }
+            }
+        }
+    }
+    // whole steps strictly between
+    if (sf + 1 + lane < sl) {
+        const int64_t gs = step0 + sf + 1 + lane;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            if (m < M) {
+                const int64_t o = (int64_t)m * S_all + gs;
+                sum[m] += gload<double>(j.step_sum, o);
+                mn[m] = fminf(mn[m], gload<float>(j.step_min, o));
+                mx[m] = fmaxf(mx[m], gload<float>(j.step_max, o));
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        if (m < M) {
+            sum[m] = wave_sum_d(sum[m]);
+            mn[m] = wave_min_f(mn[m]);
+            mx[m] = wave_max_f(mx[m]);
+        }
+    }
+}
 
-// Reduce the per-lane partials (asum, amin, amax) of one bin over the wave
-// and store the bin: a complete bin (dest 0) gets its final mean, min, max
-// and height; a tile-edge bin goes to the tile's head (dest 1) or tail
-// (dest 2) record.  Fields are taken kRedFields at a time; lane j < F reduces
-// the sums of field j in lane order, lanes 16 + j and 32 + j its minima and
-// maxima, and lanes m < F finalise field m.
-template <int MT>
-__device__ void close_bin(const ReqDev& q, int M, int64_t T, RedScratch* rs, int dest, int64_t t, int key,
-                          uint32_t first, uint32_t last, const double (&asum)[MT],
-                          const float (&amin)[MT], const float (&amax)[MT], const float* tf) {
+// Store bin `key` = cells [first, last] of tile t: a complete bin (dest 0)
+// gets its final mean, min, max and height; a tile-edge bin goes to the
+// tile's head (dest 1) or tail (dest 2) record, merged across tiles later.
+// tf: the request's tables (layout of its block).
+template <int MT, typename S>
+__device__ void close_bin(const ReqDev& q, const JobDev& j, int M, int64_t T, const RunView<MT>& view,
+                          int64_t tbase, int64_t step0, int dest, int64_t t, int key, uint32_t first,
+                          uint32_t last, const float* tf) {
+    double sm[MT];
+    float mn[MT], mx[MT];
+    range_stats<MT, S>(j, M, view, tbase, step0, first, last, sm, mn, mx);
     const int lane = lane_id();
     const uint32_t cnt = last - first + 1u;
 #pragma unroll
-    for (int m0 = 0; m0 < MT; m0 += kRedFields) {
-        if (m0 >= M) break;
-#pragma unroll
-        for (int jj = 0; jj < kRedFields; ++jj) {
-            if (m0 + jj < MT) {
-                rs->sum[jj][lane] = asum[m0 + jj];
-                rs->mn[jj][lane] = amin[m0 + jj];
-                rs->mx[jj][lane] = amax[m0 + jj];
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int nf = min(kRedFields, M - m0);
-        if (lane < nf) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            for (int l = 0; l < kWave; l += 4) {
-                s0 += rs->sum[lane][l];
-                s1 += rs->sum[lane][l + 1];
-                s2 += rs->sum[lane][l + 2];
-                s3 += rs->sum[lane][l + 3];
-            }
-            rs->rsum[lane] = (s0 + s1) + (s2 + s3);
-        } else if (lane >= 16 && lane < 16 + nf) {
-            const int jj = lane - 16;
-            float v = INFINITY;
-            for (int l = 0; l < kWave; ++l) v = fminf(v, rs->mn[jj][l]);
-            rs->rmn[jj] = v;
-        } else if (lane >= 32 && lane < 32 + nf) {
-            const int jj = lane - 32;
-            float v = -INFINITY;
-            for (int l = 0; l < kWave; ++l) v = fmaxf(v, rs->mx[jj][l]);
-            rs->rmx[jj] = v;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane < nf) {
-            const int m = m0 + lane;
-            const double sm = rs->rsum[lane];
-            const float mn = rs->rmn[lane], mx = rs->rmx[lane];
+    for (int m = 0; m < MT; ++m) {
+        if (m < M && lane == m) {
             if (dest == 0) {
-                const float mean = (float)(sm / (double)cnt);
+                const float mean = (float)(sm[m] / (double)cnt);
                 const int e = tf_entry(mean, q.s[m], q.b[m], q.nmax[m]);
                 const int64_t o = (int64_t)m * q.W + key;
                 gstore<float>(q.mean, o, mean);
-                gstore<float>(q.vmin, o, mn);
-                gstore<float>(q.vmax, o, mx);
+                gstore<float>(q.vmin, o, mn[m]);
+                gstore<float>(q.vmax, o, mx[m]);
                 gstore<float>(q.y, o, tf[q.tf_off[m] + e]);
             } else {
                 const int64_t o = ((int64_t)(dest - 1) * M + m) * T + t;
-                gstore<double>(q.ws.rec_sum, o, sm);
-                gstore<float>(q.ws.rec_min, o, mn);
-                gstore<float>(q.ws.rec_max, o, mx);
+                gstore<double>(q.ws.rec_sum, o, sm[m]);
+                gstore<float>(q.ws.rec_min, o, mn[m]);
+                gstore<float>(q.ws.rec_max, o, mx[m]);
             }
         }
-        __builtin_amdgcn_wave_barrier();
     }
     if (lane == 0) {
         if (dest == 0) {
@@ -640,19 +652,23 @@ __device__ void close_bin(const ReqDev& q, int M, int64_t T, RedScratch* rs, int
     }
 }
 
-// a bin that holds one cell only (strictly inside a wide cell)
-template <int MT>
-__device__ void write_single(const ReqDev& q, int M, int key, const float (&x)[MT], uint32_t g, const float* tf) {
+// a bin that holds one cell only (strictly inside a wide cell); called by the
+// lane owning cell g
+template <int MT, typename S>
+__device__ void write_single(const ReqDev& q, const JobDev& j, int M, int key, uint32_t g, const float* tf) {
     gstore<uint32_t>(q.first_cell, key, g);
     gstore<uint32_t>(q.last_cell, key, g);
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         if (m < M) {
-            const int e = tf_entry(x[m], q.s[m], q.b[m], q.nmax[m]);
+            Quad<S> qd;
+            qd.load(j.fields[m], (int64_t)(g >> 2));
+            const float x = qd.get((int)(g & 3u));
+            const int e = tf_entry(x, q.s[m], q.b[m], q.nmax[m]);
             const int64_t o = (int64_t)m * q.W + key;
-            gstore<float>(q.mean, o, x[m]);
-            gstore<float>(q.vmin, o, x[m]);
-            gstore<float>(q.vmax, o, x[m]);
+            gstore<float>(q.mean, o, x);
+            gstore<float>(q.vmin, o, x);
+            gstore<float>(q.vmax, o, x);
             gstore<float>(q.y, o, tf[q.tf_off[m] + e]);
         }
     }
@@ -682,12 +698,193 @@ __device__ __forceinline__ TileSpan tile_span(const ReqDev& q, const JobDev& j, 
     return sp;
 }
 
+// V of cell k of this lane (request q, tables in the request's block layout)
+template <int MT, typename S>
+__device__ __forceinline__ float rescan_v(const StepData<MT, S>& d, int k, int M, const float* tf,
+                                          const ReqDev& q, const int (&off)[MT]) {
+    float xk[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) xk[m] = m < M ? d.q[m].get(k) : 0.0f;
+    return variation<MT>(xk, M, tf, q);
+}
+template <int MT>
+__device__ __forceinline__ float rescan_v(const StepIdx<MT>& d, int k, int M, const float* tf, const ReqDev& q,
+                                          const int (&off)[MT]) {
+    float amax = -INFINITY, amin = INFINITY;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        if (m < M) {
+            const float al = tf[off[m] + (int)((d.e[m] >> (8 * k)) & 0xFFu)];
+            amax = fmaxf(amax, al);
+            amin = fminf(amin, al);
+        }
+    }
+    return amax - amin;
+}
+
+// One queued tile of request q: f of every cell again (from values or cached
+// entries, bit for bit as in K1), monotone in-tile prefix, pixel interval and
+// bins of every cell; each bin's cell range is closed as soon as it is known
+// and its statistics taken from the values at its ends and the per-step
+// statistics in between.
+template <int MT, typename S, typename D>
+__device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, int64_t t, const float* tf_lds) {
+    const int lane = lane_id();
+    const int M = uni(fields_of<MT>(j.M));
+    const int64_t T = uni(j.n_tiles);
+    const int64_t n = uni(j.n);
+    const bool degenerate = uni((int)(gload<double>(q.ws.scal, 1) != 0.0)) != 0;
+    const TileSpan sp = tile_span(q, j, t);
+    const float scale_f = uni(sp.scale_f), X0 = uni(sp.X0), X1 = uni(sp.X1);
+    const int W1 = uni(q.W) - 1;
+    const int tile_steps = uni(j.tile_steps);
+    const int64_t tile_cells = (int64_t)tile_steps * kStepCells;
+    const int64_t tbase = t * tile_cells;
+    const int64_t step0 = t * tile_steps;
+    const int64_t tend = min(tbase + tile_cells, n);
+    const uint32_t last_valid = (uint32_t)(tend - 1);
+    const int nsteps = (int)((tend - tbase + kStepCells - 1) / kStepCells);
+    const RunView<MT> vals = run_view<MT, StepData<MT, S>>(j, M, tbase);
+    const RunView<MT> view = run_view<MT, D>(j, M, tbase);
+    const ImpCtx c = make_ctx(q);
+    int off[MT];
+    table_offsets<MT>(q, M, off);
+
+    float run = 0.0f;
+    bool o_valid = false;
+    int O = -1, Bh = -1;
+    uint32_t O_first = 0;
+
+    D cur, nx1;
+    cur.load(view, M, (uint32_t)lane);
+    nx1.load(view, M, (uint32_t)(min(1, nsteps - 1) * kWave + lane));
+    for (int s = 0; s < nsteps; ++s) {
+        const int64_t c0 = tbase + (int64_t)s * kStepCells;
+        const int64_t quad = (c0 >> 2) + lane;
+        D nxt;
+        nxt.load(view, M, (uint32_t)(min(s + 2, nsteps - 1) * kWave + lane));
+
+        float f[4];
+        uint32_t g[4];
+        bool valid[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            g[k] = (uint32_t)((quad << 2) + k);
+            valid[k] = (int64_t)g[k] < n;
+            float fk = 1.0f;
+            if (!degenerate)
+                fk = importance_from_v(rescan_v<MT>(cur, k, M, tf_lds, q, off), (cur.lv >> (8 * k)) & 0xFFu, c);
+            f[k] = valid[k] ? fk : 0.0f;
+        }
+
+        // monotone in-tile prefix: lane-serial over 4 cells, wave sum scan,
+        // running max to undo rounding steps back, min-clamp inside the lane
+        const float p1 = f[0], p2 = p1 + f[1], p3 = p2 + f[2], tl = p3 + f[3];
+        const float B = wave_incl_max(wave_incl_sum(tl));
+        const float Bex = shfl_up1(B, 0.0f);
+        const float stot = readlane(B, kWave - 1);
+        float xs[5];
+        xs[0] = fminf(fmaf(run + fminf(Bex, B), scale_f, X0), X1);
+        xs[1] = fminf(fmaf(run + fminf(Bex + p1, B), scale_f, X0), X1);
+        xs[2] = fminf(fmaf(run + fminf(Bex + p2, B), scale_f, X0), X1);
+        xs[3] = fminf(fmaf(run + fminf(Bex + p3, B), scale_f, X0), X1);
+        xs[4] = fminf(fmaf(run + B, scale_f, X0), X1);
+        run = run + stot;
+
+        // pixel bins of each cell: [floor(x1), ceil(x2) - 1], clamped
+        int blo[4], bhi[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float en = (g[k] == last_valid) ? X1 : xs[k + 1];
+            blo[k] = max(0, min((int)floorf(xs[k]), W1));
+            bhi[k] = max(blo[k], min((int)ceilf(en) - 1, W1));
+        }
+
+        const bool full = c0 + kStepCells <= n;
+        const int key0 = readlane(blo[0], 0);
+        if (s == 0) Bh = key0;
+        const int key_end = full ? readlane(bhi[3], kWave - 1) : INT_MAX;
+
+        if (full && key0 == key_end && (!o_valid || key0 == O)) {
+            // the whole step lies in the open bin
+            if (!o_valid) {
+                o_valid = true;
+                O = key0;
+                O_first = (uint32_t)c0;
+            }
+            cur = nx1;
+            nx1 = nxt;
+            continue;
+        }
+
+        // ---- bin boundary inside the step ----
+        const int last_lane = full ? kWave - 1 : (int)((n - 1 - c0) >> 2);
+        const int kl = (int)((n - 1 - c0) & 3);
+        const int bhi_last = kl == 0 ? bhi[0] : (kl == 1 ? bhi[1] : (kl == 2 ? bhi[2] : bhi[3]));
+        const int key_last = full ? key_end : readlane(bhi_last, last_lane);
+        // (1) the open bin ended with the previous step
+        if (o_valid && key0 != O) {
+            close_bin<MT, S>(q, j, M, T, vals, tbase, step0, O == Bh ? 1 : 0, t, O, O_first, (uint32_t)(c0 - 1),
+                             tf_lds);
+            o_valid = false;
+        }
+        // (2) bins strictly inside a wide cell hold that cell alone
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (valid[k] && bhi[k] > blo[k] + 1)
+                for (int bb = blo[k] + 1; bb < bhi[k]; ++bb) write_single<MT, S>(q, j, M, bb, g[k], tf_lds);
+        // (3) every bin that is the first or last bin of some cell of this
+        //     step, in increasing order; all but the step's last one close
+        int b = key0;
+        while (true) {
+            uint32_t gmin = 0xFFFFFFFFu, gmax = 0u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (valid[k] && (blo[k] == b || bhi[k] == b)) {
+                    gmin = min(gmin, g[k]);
+                    gmax = max(gmax, g[k]);
+                }
+            }
+            const uint32_t bfirst = (o_valid && b == O) ? O_first : wave_min_u32(gmin);
+            if (b == key_last) {
+                // stays open into the next step
+                O = b;
+                O_first = bfirst;
+                o_valid = true;
+                break;
+            }
+            close_bin<MT, S>(q, j, M, T, vals, tbase, step0, b == Bh ? 1 : 0, t, b, bfirst, wave_max_u32(gmax),
+                             tf_lds);
+            o_valid = false;
+            int nk = INT_MAX;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (valid[k]) {
+                    if (blo[k] > b) nk = min(nk, blo[k]);
+                    if (bhi[k] > b) nk = min(nk, bhi[k]);
+                }
+            }
+            b = wave_min_i32(nk);
+            if (b == INT_MAX) break;   // cannot happen: key_last is above
+        }
+        cur = nx1;
+        nx1 = nxt;
+    }
+
+    // tile end: the open bin is the tile's last bin
+    if (o_valid) {
+        close_bin<MT, S>(q, j, M, T, vals, tbase, step0, O == Bh ? 1 : 2, t, O, O_first, last_valid, tf_lds);
+        if (lane == 0) {
+            gstore<int32_t>(q.ws.head_bin, t, Bh);
+            gstore<int32_t>(q.ws.tail_bin, t, O);
+        }
+    }
+}
+
 // K3b: the queued tiles, one wave each.
 template <int MT, typename S>
 __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
-    extern __shared__ float lds[];
-    RedScratch* rs = reinterpret_cast<RedScratch*>(lds);
-    float* tf_lds = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + (kRedBytes + 15) / 16 * 16);
+    extern __shared__ float tf_lds[];
     const int lane = lane_id();
     int loaded = -1;
     const int64_t n_queued = gload<uint32_t>(bd.rescan_count, 0);
@@ -698,20 +895,6 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
         const ReqDev& q = bd.reqs[qi];
         const JobDev& j = bd.jobs[uni(q.job)];
         const int64_t t = u - uni(q.k3_unit0);
-        const int M = uni(fields_of<MT>(j.M));
-        const int64_t T = uni(j.n_tiles);
-        const int64_t n = uni(j.n);
-        const bool degenerate = uni((int)(gload<double>(q.ws.scal, 1) != 0.0)) != 0;
-        const TileSpan sp = tile_span(q, j, t);
-        const float scale_f = uni(sp.scale_f), X0 = uni(sp.X0), X1 = uni(sp.X1);
-        const int W1 = uni(q.W) - 1;
-        const int64_t tile_cells = (int64_t)uni(j.tile_steps) * kStepCells;
-        const int64_t tbase = t * tile_cells;
-        const int64_t tend = min(tbase + tile_cells, n);
-        const uint32_t last_valid = (uint32_t)(tend - 1);
-        const int nsteps = (int)((tend - tbase + kStepCells - 1) / kStepCells);
-        const RunView<MT> view = run_view<MT, StepData<MT, S>>(j, M, tbase);
-
         // the tile is rescanned: this request's tables in LDS
         if (qi != loaded) {
             __builtin_amdgcn_wave_barrier();
@@ -721,193 +904,10 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             loaded = qi;
         }
-        const ImpCtx c = make_ctx(q);
-
-        float run = 0.0f;
-        bool o_valid = false;
-        int O = -1, Bh = -1;
-        uint32_t O_first = 0, O_last = 0;
-        double asum[MT];
-        float amin[MT], amax[MT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            asum[m] = 0.0;
-            amin[m] = INFINITY;
-            amax[m] = -INFINITY;
-        }
-
-        StepData<MT, S> cur, nx1;
-        cur.load(view, M, (uint32_t)lane);
-        nx1.load(view, M, (uint32_t)(min(1, nsteps - 1) * kWave + lane));
-        for (int s = 0; s < nsteps; ++s) {
-            const int64_t c0 = tbase + (int64_t)s * kStepCells;
-            const int64_t quad = (c0 >> 2) + lane;
-            StepData<MT, S> nxt;
-            nxt.load(view, M, (uint32_t)(min(s + 2, nsteps - 1) * kWave + lane));
-
-            float x[MT][4];
-            float f[4];
-            uint32_t g[4];
-            bool valid[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                float xk[MT];
-#pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    xk[m] = m < M ? cur.q[m].get(k) : 0.0f;
-                    x[m][k] = xk[m];
-                }
-                g[k] = (uint32_t)((quad << 2) + k);
-                valid[k] = (int64_t)g[k] < n;
-                float fk = 1.0f;
-                if (!degenerate) fk = importance_from_v(variation<MT>(xk, M, tf_lds, q),
-                                                        (cur.lv >> (8 * k)) & 0xFFu, c);
-                f[k] = valid[k] ? fk : 0.0f;
-            }
-
-            // monotone in-tile prefix: lane-serial over 4 cells, wave sum scan,
-            // running max to undo rounding steps back, min-clamp inside the lane
-            const float p1 = f[0], p2 = p1 + f[1], p3 = p2 + f[2], tl = p3 + f[3];
-            const float B = wave_incl_max(wave_incl_sum(tl));
-            const float Bex = shfl_up1(B, 0.0f);
-            const float stot = readlane(B, kWave - 1);
-            float xs[5];
-            xs[0] = fminf(fmaf(run + fminf(Bex, B), scale_f, X0), X1);
-            xs[1] = fminf(fmaf(run + fminf(Bex + p1, B), scale_f, X0), X1);
-            xs[2] = fminf(fmaf(run + fminf(Bex + p2, B), scale_f, X0), X1);
-            xs[3] = fminf(fmaf(run + fminf(Bex + p3, B), scale_f, X0), X1);
-            xs[4] = fminf(fmaf(run + B, scale_f, X0), X1);
-            run = run + stot;
-
-            // pixel bins of each cell: [floor(x1), ceil(x2) - 1], clamped
-            int blo[4], bhi[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float en = (g[k] == last_valid) ? X1 : xs[k + 1];
-                blo[k] = max(0, min((int)floorf(xs[k]), W1));
-                bhi[k] = max(blo[k], min((int)ceilf(en) - 1, W1));
-            }
-
-            const bool full = c0 + kStepCells <= n;
-            const int key0 = readlane(blo[0], 0);
-            if (s == 0) Bh = key0;
-            const int key_end = full ? readlane(bhi[3], kWave - 1) : INT_MAX;
-
-            if (full && key0 == key_end && (!o_valid || key0 == O)) {
-                // the whole step lies in one bin: per-lane accumulation
-                if (!o_valid) {
-                    o_valid = true;
-                    O = key0;
-                    O_first = (uint32_t)c0;
-                }
-                O_last = (uint32_t)(c0 + kStepCells - 1);
-#pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    if (m < M) {
-                        const float s4 = (x[m][0] + x[m][1]) + (x[m][2] + x[m][3]);
-                        asum[m] += (double)s4;
-                        amin[m] = fminf(amin[m], fminf(fminf(x[m][0], x[m][1]), fminf(x[m][2], x[m][3])));
-                        amax[m] = fmaxf(amax[m], fmaxf(fmaxf(x[m][0], x[m][1]), fmaxf(x[m][2], x[m][3])));
-                    }
-                }
-                cur = nx1;
-                nx1 = nxt;
-                continue;
-            }
-
-            // ---- bin boundary inside the step ----
-            const int last_lane = full ? kWave - 1 : (int)((n - 1 - c0) >> 2);
-            const int kl = (int)((n - 1 - c0) & 3);
-            const int bhi_last = kl == 0 ? bhi[0] : (kl == 1 ? bhi[1] : (kl == 2 ? bhi[2] : bhi[3]));
-            const int key_last = full ? key_end : readlane(bhi_last, last_lane);
-            // (1) the open bin ended with the previous step: reduce and emit it
-            if (o_valid && key0 != O) {
-                close_bin<MT>(q, M, T, rs, O == Bh ? 1 : 0, t, O, O_first, O_last, asum, amin, amax, tf_lds);
-                o_valid = false;
-            }
-            // (2) bins strictly inside a wide cell hold that cell alone
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (valid[k] && bhi[k] > blo[k] + 1) {
-                    float xk[MT];
-#pragma unroll
-                    for (int m = 0; m < MT; ++m) xk[m] = x[m][k];
-                    for (int bb = blo[k] + 1; bb < bhi[k]; ++bb) write_single<MT>(q, M, bb, xk, g[k], tf_lds);
-                }
-            }
-            // (3) every bin that is the first or last bin of some cell of this
-            //     step, in increasing order; all but the step's last one close
-            int b = key0;
-            while (true) {
-                bool in[4];
-                uint32_t gmin = 0xFFFFFFFFu, gmax = 0u;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    in[k] = valid[k] && (blo[k] == b || bhi[k] == b);
-                    if (in[k]) {
-                        gmin = min(gmin, g[k]);
-                        gmax = max(gmax, g[k]);
-                    }
-                }
-                const bool cont = o_valid && b == O;   // continues the open bin
-                if (!cont) {
-#pragma unroll
-                    for (int m = 0; m < MT; ++m) {
-                        asum[m] = 0.0;
-                        amin[m] = INFINITY;
-                        amax[m] = -INFINITY;
-                    }
-                }
-#pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    if (m < M) {
-                        float s4 = 0.0f;
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            if (in[k]) {
-                                s4 += x[m][k];
-                                amin[m] = fminf(amin[m], x[m][k]);
-                                amax[m] = fmaxf(amax[m], x[m][k]);
-                            }
-                        }
-                        asum[m] += (double)s4;
-                    }
-                }
-                const uint32_t bfirst = cont ? O_first : wave_min_u32(gmin);
-                if (b == key_last) {
-                    // stays open into the next step (per-lane accumulators keep it)
-                    O = b;
-                    O_first = bfirst;
-                    O_last = (uint32_t)min((int64_t)c0 + kStepCells - 1, n - 1);
-                    o_valid = true;
-                    break;
-                }
-                close_bin<MT>(q, M, T, rs, b == Bh ? 1 : 0, t, b, bfirst, wave_max_u32(gmax), asum, amin, amax,
-                              tf_lds);
-                o_valid = false;
-                int nk = INT_MAX;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (valid[k]) {
-                        if (blo[k] > b) nk = min(nk, blo[k]);
-                        if (bhi[k] > b) nk = min(nk, bhi[k]);
-                    }
-                }
-                b = wave_min_i32(nk);
-                if (b == INT_MAX) break;   // cannot happen: key_last is above
-            }
-            cur = nx1;
-            nx1 = nxt;
-        }
-
-        // tile end: the open bin is the tile's last bin
-        if (o_valid) {
-            close_bin<MT>(q, M, T, rs, O == Bh ? 1 : 2, t, O, O_first, O_last, asum, amin, amax, tf_lds);
-            if (lane == 0) {
-                gstore<int32_t>(q.ws.head_bin, t, Bh);
-                gstore<int32_t>(q.ws.tail_bin, t, O);
-            }
-        }
+        if (j.idx[0])
+            rescan_tile<MT, S, StepIdx<MT>>(q, j, t, tf_lds);
+        else
+            rescan_tile<MT, S, StepData<MT, S>>(q, j, t, tf_lds);
     }
 }
 
@@ -951,7 +951,7 @@ static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEv
     if (dvl_status st = launch_carry(b, s)) return st;
     if (dvl_status st = mark(3)) return st;
     if (dvl_status st = launch_classify(b, s)) return st;
-    const size_t lds3 = (kRedBytes + 15) / 16 * 16 + (size_t)b.max_req_tf * sizeof(float);
+    const size_t lds3 = (size_t)b.max_req_tf * sizeof(float);
     const unsigned g3 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.k3_units, (int64_t)n_cu * 16));
     hipLaunchKernelGGL((k_bin<MT, S>), dim3(g3), dim3(kBinThreads), lds3, s, b);
     DVL_HIP(hipGetLastError());
