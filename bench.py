@@ -48,13 +48,16 @@ def make_workload(name: str, base: int | None, device: str):
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the HIP sources, the build script and the C header (the
-    inputs of libdvl.so); profiles record it next to their counters."""
+    """sha256 over the device-code sources (the kernels and what they include)
+    and the build script's flags; profiles record it next to their counters.
+    Host-side launch code (api.hip) is not part of it: it does not change the
+    bytes a kernel moves."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2306_11612_amd", "csrc", "*")))
-    files += [os.path.join(ROOT, "paper_2306_11612_amd", "build.py"), os.path.join(ROOT, "include", "dvl.h")]
+    csrc = os.path.join(ROOT, "paper_2306_11612_amd", "csrc")
+    files = sorted(f for f in glob.glob(os.path.join(csrc, "*")) if os.path.basename(f) != "api.hip")
+    files += [os.path.join(ROOT, "paper_2306_11612_amd", "build.py")]
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -100,7 +103,8 @@ def cpu_baseline(V, alphas, n_bins: int, sample: int, exponent: float, fmin: flo
 def bench_batch32(args, dt):
     """32 resident volumes of 1-20 M cells (8 fields, W = 2048), every volume
     updated after a TF change each step: as 32 sequential dvl_update calls, as
-    one dvl_update_batch, and as one captured graph (dvl_graph_launch)."""
+    one dvl_update_batch, and as one captured graph (dvl_graph_launch);
+    `value` is the faster of the two batched forms."""
     import numpy as np
     import torch
     import synth
@@ -174,9 +178,10 @@ def bench_batch32(args, dt):
     elem = 4 if args.dtype == "f32" else 2
     bpc = (M + 1) if cached else (M * elem + 1)
     achieved = cells * bpc / (per_launch["tile_sums"] * 1e-3) / 1e9
+    ms_best = min(ms_batch, ms_graph)
     out = {
-        "metric": METRIC, "value": cells / (ms_graph * 1e-3), "unit": "cells/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True,
+        "metric": METRIC, "value": cells / (ms_best * 1e-3), "unit": "cells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_best, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": "batch32: 32 AMR volumes of 1-20 M cells (log-uniform), 2-4 levels, 8 fields, "
                                "one TF change per volume per step", "n_volumes": n_vol, "n_cells": cells,
@@ -187,7 +192,7 @@ def bench_batch32(args, dt):
                      "bytes_per_cell": bpc, "avg_launch_ms": per_launch["tile_sums"]},
         "entry_cache": cached,
         "sequential_ms_per_step": ms_seq, "batch_ms_per_step": ms_batch, "graph_ms_per_step": ms_graph,
-        "speedup_graph_vs_sequential": ms_seq / ms_graph,
+        "speedup_vs_sequential": ms_seq / ms_best,
         "kernel_ms_per_batch": per_launch, "generation_s": gen_s,
     }
     g.close()

@@ -335,8 +335,8 @@ struct Plan {
     int64_t k1_units = 0, k3_units = 0, k4_units = 0;
     size_t tf_floats = 0;
     // descriptor block, uploaded before every launch:
-    //   [header: rescan counter][JobDev x jobs][ReqDev x reqs][max V x reqs][tables]
-    // followed on the device (not uploaded) by the rescan queue [k3_units]
+    //   [header: 3 rescan counters][JobDev x jobs][ReqDev x reqs][max V x reqs][tables]
+    // followed on the device (not uploaded) by the rescan queues [3][k3_units]
     size_t off_jobs = 0, off_reqs = 0, off_vmax = 0, off_tf = 0, block_bytes = 0;
     size_t off_queue = 0, device_bytes = 0;
 };
@@ -451,7 +451,7 @@ static dvl_status plan_batch(std::vector<ReqHost>&& reqs, Plan& P) {
     P.off_tf = P.off_vmax + al256(P.rdev.size() * sizeof(float));
     P.block_bytes = P.off_tf + al256(P.tf_floats * sizeof(float));
     P.off_queue = P.block_bytes;
-    P.device_bytes = P.off_queue + al256((size_t)P.k3_units * sizeof(uint64_t));
+    P.device_bytes = P.off_queue + al256((size_t)3 * P.k3_units * sizeof(uint64_t));
     return DVL_OK;
 }
 
@@ -475,7 +475,7 @@ static dvl_status fill_block(Plan& P, char* h, char* d) {
         P.rdev[q].vmax_dev = (float*)(d + P.off_vmax) + q;
     }
     for (auto& j : P.jobs) j.tf_all = (const float*)(d + P.off_tf) + P.reqs[j.req0].tf_pos;
-    memset(h, 0, P.off_jobs);   // rescan counter starts at 0
+    memset(h, 0, P.off_jobs);   // rescan counters start at 0
     memcpy(h + P.off_jobs, P.jobs.data(), P.jobs.size() * sizeof(JobDev));
     memcpy(h + P.off_reqs, P.rdev.data(), P.rdev.size() * sizeof(ReqDev));
     return DVL_OK;
@@ -591,7 +591,12 @@ static BatchDev batch_dev(const Plan& P, char* d, int paths) {
     return b;
 }
 
-static size_t request_ws_bytes(const dvl_volume* v) { return workspace_bytes(v->n_tiles, v->M); }
+static int64_t fstore_cells(const dvl_volume* v, int n_bins) {
+    return wants_fstore(v->n_tiles, n_bins) ? v->n_pad : 0;
+}
+static size_t request_ws_bytes(const dvl_volume* v, int n_bins) {
+    return workspace_bytes(v->n_tiles, v->M, fstore_cells(v, n_bins));
+}
 
 // ================================================================== executor
 
@@ -704,8 +709,9 @@ struct Executor {
 
     dvl_status run(Plan& P, hipStream_t s) {
         for (size_t q = 0; q < P.reqs.size(); ++q) {
-            if (dvl_status st = ensure_ws(q, request_ws_bytes(P.reqs[q].v))) return st;
-            workspace_carve(ws[q].first, P.reqs[q].v->n_tiles, P.reqs[q].v->M, &P.rdev[q].ws);
+            const ReqHost& r = P.reqs[q];
+            if (dvl_status st = ensure_ws(q, request_ws_bytes(r.v, r.p.n_bins))) return st;
+            workspace_carve(ws[q].first, r.v->n_tiles, r.v->M, fstore_cells(r.v, r.p.n_bins), &P.rdev[q].ws);
         }
         std::vector<CacheBuild> builds;
         if (dvl_status st = decide_cache(P, builds)) return st;
@@ -720,6 +726,8 @@ struct Executor {
         if (dvl_status st = timing_events(&ev)) return st;
         int paths = 0;
         for (const JobDev& j : P.jobs) paths |= j.idx[0] ? kPathEntries : kPathValues;
+        for (const ReqDev& d : P.rdev)
+            if (d.ws.fstore) paths |= kPathStoredF;
         return launch_batch(batch_dev(P, slot->dev, paths), P.dtype, P.max_m, P.max_req, n_cu, s, ev);
     }
 
@@ -810,16 +818,16 @@ extern "C" {
 const char* dvl_last_error(void) { return g_err.c_str(); }
 
 size_t dvl_update_workspace_bytes(int64_t n_cells, int32_t n_fields, int32_t n_bins) {
-    (void)n_bins;
-    if (n_cells < 1 || n_fields < 1) return 0;
+    if (n_cells < 1 || n_fields < 1 || n_bins < 1) return 0;
     const int64_t cells = (int64_t)kDefaultTileSteps * kStepCells;
-    return workspace_bytes((n_cells + cells - 1) / cells, n_fields);
+    const int64_t T = (n_cells + cells - 1) / cells;
+    return workspace_bytes(T, n_fields, wants_fstore(T, n_bins) ? T * cells : 0);
 }
 
 size_t dvl_request_bytes(const dvl_volume* v, int32_t n_bins) {
     if (!v || n_bins < 1) return 0;
     // workspace + outputs (first/last, mean/min/max/y per field, two scalars)
-    return request_ws_bytes(v) + (size_t)n_bins * (8 + 16 * (size_t)v->M) + 16;
+    return request_ws_bytes(v, n_bins) + (size_t)n_bins * (8 + 16 * (size_t)v->M) + 16;
 }
 
 dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, const int32_t* z,
@@ -863,8 +871,9 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
     DVL_HIP(hipGetDevice(&v->device));
     DVL_HIP(hipDeviceGetAttribute(&v->n_cu, hipDeviceAttributeMultiprocessorCount, v->device));
     {
-        // runs of consecutive tiles, one per wave of the importance pass
-        const int64_t waves = run_waves ? run_waves : (int64_t)v->n_cu * 32;
+        // runs of consecutive tiles, one per wave of the importance pass; the
+        // default (16 per compute unit) fits one round of resident waves
+        const int64_t waves = run_waves ? run_waves : (int64_t)v->n_cu * 16;
         v->tiles_per_run = std::max<int64_t>(1, (v->n_tiles + waves - 1) / waves);
         v->n_runs = (v->n_tiles + v->tiles_per_run - 1) / v->tiles_per_run;
     }
@@ -961,7 +970,7 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
 
     // private executor of dvl_update, with the workspace of one request ready
     if (dvl_status st = new_executor(&v->ex)) return st;
-    if (dvl_status st = v->ex->ensure_ws(0, request_ws_bytes(v))) return st;
+    if (dvl_status st = v->ex->ensure_ws(0, request_ws_bytes(v, 1))) return st;
     guard.v = nullptr;
     *out = v;
     return DVL_OK;
@@ -1221,9 +1230,10 @@ dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph**
     DVL_HIP(hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     for (size_t q = 0; q < P.reqs.size(); ++q) {
         DevBuf w;
-        if (dvl_status st = w.alloc(request_ws_bytes(P.reqs[q].v), "request workspace")) return st;
+        const ReqHost& r = P.reqs[q];
+        if (dvl_status st = w.alloc(request_ws_bytes(r.v, r.p.n_bins), "request workspace")) return st;
         g->ws.push_back(w.release());
-        workspace_carve(g->ws.back(), P.reqs[q].v->n_tiles, P.reqs[q].v->M, &P.rdev[q].ws);
+        workspace_carve(g->ws.back(), r.v->n_tiles, r.v->M, fstore_cells(r.v, r.p.n_bins), &P.rdev[q].ws);
     }
     DevBuf d;
     if (dvl_status st = d.alloc(P.device_bytes, "graph descriptors")) return st;
@@ -1248,7 +1258,7 @@ dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph**
         (void)hipStreamDestroy(cs);
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    const dvl_status cst = launch_batch(batch_dev(P, g->dev, kPathValues | kPathEntries), P.dtype, P.max_m,
+    const dvl_status cst = launch_batch(batch_dev(P, g->dev, kPathValues | kPathEntries | kPathStoredF), P.dtype, P.max_m,
                                         P.max_req, g->n_cu, cs, nullptr);
     const hipError_t ee = hipStreamEndCapture(cs, &g->graph);
     (void)hipStreamDestroy(cs);

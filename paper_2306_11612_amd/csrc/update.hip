@@ -39,7 +39,7 @@ namespace dvl {
 
 static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t workspace_bytes(int64_t T, int M) {
+size_t workspace_bytes(int64_t T, int M, int64_t fcells) {
     size_t b = 0;
     b += al256((size_t)T * 8);             // local_prefix
     b += al256((size_t)T * 8);             // run_total
@@ -49,10 +49,11 @@ size_t workspace_bytes(int64_t T, int M) {
     b += al256((size_t)2 * M * T * 8);     // rec_sum
     b += 2 * al256((size_t)2 * M * T * 4); // rec min/max
     b += al256(8 * 8);                     // scalars
+    b += al256((size_t)fcells * 4);        // stored importance
     return b;
 }
 
-void workspace_carve(void* base, int64_t T, int M, UpdWorkspace* w) {
+void workspace_carve(void* base, int64_t T, int M, int64_t fcells, UpdWorkspace* w) {
     char* p = (char*)base;
     auto take = [&](size_t bytes) { char* q = p; p += al256(bytes); return (void*)q; };
     w->local_prefix = (double*)take((size_t)T * 8);
@@ -66,6 +67,7 @@ void workspace_carve(void* base, int64_t T, int M, UpdWorkspace* w) {
     w->rec_min = (float*)take((size_t)2 * M * T * 4);
     w->rec_max = (float*)take((size_t)2 * M * T * 4);
     w->scal = (double*)take(8 * 8);
+    w->fstore = fcells ? (float*)take((size_t)fcells * 4) : nullptr;
 }
 
 // ------------------------------------------------------------------ K2
@@ -222,9 +224,11 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(BatchDev b) {
 __global__ __launch_bounds__(256) void k_classify(BatchDev bd) {
     const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
     bool need = false;
+    int path = 0;
     if (u < bd.k3_units) {
         const ReqDev& q = bd.reqs[find_req_k3(bd, u)];
         const JobDev& j = bd.jobs[q.job];
+        path = q.ws.fstore ? 2 : (j.idx[0] ? 1 : 0);
         const int64_t t = u - q.k3_unit0;
         const int64_t T = j.n_tiles;
         const TileSpan sp = tile_span(q, j, t);
@@ -245,13 +249,20 @@ __global__ __launch_bounds__(256) void k_classify(BatchDev bd) {
             need = true;
         }
     }
-    const uint64_t mask = __ballot(need);
-    if (mask) {
-        const int leader = __ffsll((unsigned long long)mask) - 1;
-        uint32_t base = 0;
-        if (lane_id() == leader) base = atomicAdd(bd.rescan_count, (uint32_t)__popcll(mask));
-        base = readlane(base, leader);
-        if (need) gstore<uint64_t>(bd.rescan_queue, base + (uint32_t)__popcll(mask & lanemask_lt()), (uint64_t)u);
+    // one queue per projection path (values, cached entries, stored f)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const bool mine = need && path == p;
+        const uint64_t mask = __ballot(mine);
+        if (mask) {
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            uint32_t base = 0;
+            if (lane_id() == leader) base = atomicAdd(bd.rescan_count + p, (uint32_t)__popcll(mask));
+            base = readlane(base, leader);
+            if (mine)
+                gstore<uint64_t>(bd.rescan_queue, p * bd.k3_units + base + (uint32_t)__popcll(mask & lanemask_lt()),
+                                 (uint64_t)u);
+        }
     }
 }
 

@@ -18,6 +18,7 @@ constexpr int kMaxReqPerJob = 8;
 constexpr int kPhases = 5;                       // exact vmax, tile sums, carry, bin, edges
 constexpr int kPathValues = 1;                   // jobs that read the field values
 constexpr int kPathEntries = 2;                  // jobs that read cached TF entries
+constexpr int kPathStoredF = 4;                  // requests whose projection reads stored f
 constexpr int kIdxTable = 256;                   // LDS floats per table on the cached-entry path
 
 // Workspace of one request on a volume of T tiles and M fields.
@@ -33,10 +34,17 @@ struct UpdWorkspace {
     float* rec_min;       // [2][M][T]
     float* rec_max;       // [2][M][T]
     double* scal;         // [0] F_tot, [1] degenerate (0/1)
+    float* fstore;        // [n_pad] importance of every cell, or NULL (see wants_fstore)
 };
 
-size_t workspace_bytes(int64_t n_tiles, int M);
-void workspace_carve(void* base, int64_t n_tiles, int M, UpdWorkspace* w);
+// fcells: cells of the stored importance (0: none)
+size_t workspace_bytes(int64_t n_tiles, int M, int64_t fcells = 0);
+void workspace_carve(void* base, int64_t n_tiles, int M, int64_t fcells, UpdWorkspace* w);
+
+// Whether a request stores f in the importance pass for the projection to
+// reuse: worth its 4 B per cell once about a quarter or more of the tiles
+// hold a bin edge (the projection then rescans most of the volume).
+inline bool wants_fstore(int64_t n_tiles, int n_bins) { return (int64_t)n_bins * 4 >= n_tiles; }
 
 // One request: TF tables, quantisers, parameters, workspace and outputs.
 struct ReqDev {
@@ -99,8 +107,8 @@ struct JobDev {
 struct BatchDev {
     const JobDev* jobs;
     const ReqDev* reqs;
-    uint32_t* rescan_count;   // tiles queued for a rescan (0 when the descriptors are uploaded)
-    uint64_t* rescan_queue;   // [k3_units] projection units of the queued tiles
+    uint32_t* rescan_count;   // [3] tiles queued for a rescan per projection path (0 when uploaded)
+    uint64_t* rescan_queue;   // [3][k3_units] projection units of the queued tiles, per path
     int n_jobs;
     int n_reqs;
     int64_t k1_units;

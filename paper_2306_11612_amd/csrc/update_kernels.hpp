@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 namespace dvl {
 
@@ -163,6 +164,18 @@ struct StepIdx {
         for (int m = 0; m < MT; ++m)
             if (m < M) e[m] = gload_at<uint32_t>(v.base[m], qd * 4u);
         lv = gload_at<uint32_t>(v.lev, qd * 4u);
+    }
+};
+
+// the importance of the 4 cells of this lane, as the importance pass stored
+// it (view.base[0]: the request's stored f)
+template <int MT>
+struct StepF {
+    static constexpr uint32_t kQuadBytes = 16;
+    f32x4 fv;
+    uint32_t lv;
+    __device__ __forceinline__ void load(const RunView<MT>& v, int M, uint32_t qd) {
+        fv = gload_at<f32x4>(v.base[0], qd * kQuadBytes);
     }
 };
 
@@ -372,12 +385,15 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
     RunAcc run[KR];
     double prev[KR], tacc[KR];
     int toff[KR], off[KR][MT];
+    float* fst[KR];                   // where f of every cell is kept for the projection, or NULL
 #pragma unroll
     for (int q = 0; q < KR; ++q) {
+        fst[q] = nullptr;
         if (q < nreq) {
             ctx[q] = make_ctx(rq[q]);
             toff[q] = uni(rq[q].tf_job_off);
             table_offsets<MT>(rq[q], M, off[q]);
+            fst[q] = uni(rq[q].ws.fstore);
         }
         run[q].init();
         prev[q] = 0.0;
@@ -414,6 +430,14 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
                     if (!full) {
 #pragma unroll
                         for (int k = 0; k < 4; ++k) f[k] = ((quad << 2) + k < n) ? f[k] : 0.0f;
+                    }
+                    if (fst[q]) {
+                        f32x4 fv;
+                        fv.x = f[0];
+                        fv.y = f[1];
+                        fv.z = f[2];
+                        fv.w = f[3];
+                        gstore<f32x4>(fst[q], quad, fv);
                     }
                     tacc[q] += (double)((f[0] + f[1]) + (f[2] + f[3]));
                 }
@@ -745,7 +769,13 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
     const uint32_t last_valid = (uint32_t)(tend - 1);
     const int nsteps = (int)((tend - tbase + kStepCells - 1) / kStepCells);
     const RunView<MT> vals = run_view<MT, StepData<MT, S>>(j, M, tbase);
-    const RunView<MT> view = run_view<MT, D>(j, M, tbase);
+    RunView<MT> view;
+    if constexpr (std::is_same<D, StepF<MT>>::value) {
+        view = vals;
+        view.base[0] = reinterpret_cast<const char*>(uni(q.ws.fstore)) + tbase * 4;
+    } else {
+        view = run_view<MT, D>(j, M, tbase);
+    }
     const ImpCtx c = make_ctx(q);
     int off[MT];
     table_offsets<MT>(q, M, off);
@@ -772,8 +802,13 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
             g[k] = (uint32_t)((quad << 2) + k);
             valid[k] = (int64_t)g[k] < n;
             float fk = 1.0f;
-            if (!degenerate)
-                fk = importance_from_v(rescan_v<MT>(cur, k, M, tf_lds, q, off), (cur.lv >> (8 * k)) & 0xFFu, c);
+            if constexpr (std::is_same<D, StepF<MT>>::value) {
+                if (!degenerate) fk = k == 0 ? cur.fv.x : (k == 1 ? cur.fv.y : (k == 2 ? cur.fv.z : cur.fv.w));
+            } else {
+                if (!degenerate)
+                    fk = importance_from_v(rescan_v<MT>(cur, k, M, tf_lds, q, off), (cur.lv >> (8 * k)) & 0xFFu,
+                                           c);
+            }
             f[k] = valid[k] ? fk : 0.0f;
         }
 
@@ -881,16 +916,19 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
     }
 }
 
-// K3b: the queued tiles, one wave each.
-template <int MT, typename S>
+// K3b: the queued tiles, one wave each.  IDX: this instance serves the
+// requests whose projection reads values (0), cached entries (1) or the f the
+// importance pass stored (2); each skips the others' tiles.
+template <int MT, typename S, int IDX>
 __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
     extern __shared__ float tf_lds[];
     const int lane = lane_id();
     int loaded = -1;
-    const int64_t n_queued = gload<uint32_t>(bd.rescan_count, 0);
+    const int64_t n_queued = gload<uint32_t>(bd.rescan_count, IDX);
+    const uint64_t* queue = bd.rescan_queue + IDX * bd.k3_units;
 
     for (int64_t i = blockIdx.x; i < n_queued; i += gridDim.x) {
-        const int64_t u = uni((int64_t)gload<uint64_t>(bd.rescan_queue, i));
+        const int64_t u = uni((int64_t)gload<uint64_t>(queue, i));
         const int qi = uni(find_req_k3(bd, u));
         const ReqDev& q = bd.reqs[qi];
         const JobDev& j = bd.jobs[uni(q.job)];
@@ -904,7 +942,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             loaded = qi;
         }
-        if (j.idx[0])
+        if constexpr (IDX == 2)
+            rescan_tile<MT, S, StepF<MT>>(q, j, t, tf_lds);
+        else if constexpr (IDX == 1)
             rescan_tile<MT, S, StepIdx<MT>>(q, j, t, tf_lds);
         else
             rescan_tile<MT, S, StepData<MT, S>>(q, j, t, tf_lds);
@@ -953,8 +993,18 @@ static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEv
     if (dvl_status st = launch_classify(b, s)) return st;
     const size_t lds3 = (size_t)b.max_req_tf * sizeof(float);
     const unsigned g3 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.k3_units, (int64_t)n_cu * 16));
-    hipLaunchKernelGGL((k_bin<MT, S>), dim3(g3), dim3(kBinThreads), lds3, s, b);
-    DVL_HIP(hipGetLastError());
+    if (b.paths & kPathValues) {
+        hipLaunchKernelGGL((k_bin<MT, S, 0>), dim3(g3), dim3(kBinThreads), lds3, s, b);
+        DVL_HIP(hipGetLastError());
+    }
+    if (b.paths & kPathEntries) {
+        hipLaunchKernelGGL((k_bin<MT, S, 1>), dim3(g3), dim3(kBinThreads), lds3, s, b);
+        DVL_HIP(hipGetLastError());
+    }
+    if (b.paths & kPathStoredF) {
+        hipLaunchKernelGGL((k_bin<MT, S, 2>), dim3(g3), dim3(kBinThreads), lds3, s, b);
+        DVL_HIP(hipGetLastError());
+    }
     if (dvl_status st = mark(4)) return st;
     if (dvl_status st = launch_edges(b, MT, s)) return st;
     return mark(5);

@@ -275,6 +275,16 @@ def test_cfg2_scaled(cfg2_base64, W, exponent):
              label=f"cfg2/base64 W={W}")
 
 
+@pytest.mark.parametrize("W", [16, 48, 300])
+def test_entry_cache_projection_paths(cfg2_base64, W):
+    """The projection from cached entries (few bins: most tiles take their
+    precomputed statistics, the rest are rescanned from entries) and from the
+    importance the first pass stored (bins >= a quarter of the tiles)."""
+    import synth
+    run_case(cfg2_base64, tfs(synth.SEED + 5, 4, n_cp=(4, 8)), W, exponent=1.5, entry_cache=1,
+             label=f"cfg2/base64 entries W={W}")
+
+
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
 def test_sixteen_bit_few_bins(cfg2_base64, dtype):
     import synth
