@@ -217,6 +217,23 @@ def test_ragged_cell_counts(n):
     run_case(vol, tfs(n, 2), 64, label=f"ragged {n}")
 
 
+@pytest.mark.parametrize("n_fields,n_tf", [(16, 1024), (4, 4096), (5, 256), (8, 256), (3, 300)])
+def test_field_and_table_limits(n_fields, n_tf):
+    """The most fields (16) and the largest tables (4096 entries; 16 * 1024 =
+    16384 floats in all), field counts served by the general kernel variant
+    (3, 5, 16) and by the fixed ones (8), tables too large for the entry cache."""
+    vol = random_amr(17, 6, 3, 0.4, n_fields=n_fields)
+    run_case(vol, tfs(n_fields * 7 + n_tf, n_fields, n_tf=n_tf), 500, exponent=1.5,
+             label=f"M={n_fields} n_tf={n_tf}")
+
+
+def test_most_bins():
+    """W = 2^20 bins over ~2.6 k cells: every cell spans hundreds of bins."""
+    vol = random_amr(18, 4, 3, 0.4, n_fields=2)
+    g, _, _ = run_case(vol, tfs(18, 2), 1 << 20, label="W=2^20")
+    assert np.all(g["count"] >= 1)
+
+
 def test_more_bins_than_cells():
     """Cells wider than a pixel: interior bins hold exactly one cell."""
     vol = random_amr(11, 6, 3, 0.4, n_fields=3)
