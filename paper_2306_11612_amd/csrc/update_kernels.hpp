@@ -571,8 +571,8 @@ __device__ __forceinline__ double tile_offset(const JobDev& j, const UpdWorkspac
 
 // Field statistics of the sorted cells [first, last] of one tile (tbase: its
 // first cell; view: its streams), computed by the whole wave from the stored
-// values of the partial 256-cell steps at both ends and the per-step
-// statistics of the steps in between (at most tile_steps - 2 < 64 of them,
+// values of the partial 256-cell steps at its ends and the per-step
+// statistics of the steps it covers whole (at most tile_steps <= 64 of them,
 // one per lane).  Sums are fp64; every lane ends with the result.
 template <int MT, typename S>
 __device__ __forceinline__ void range_stats(const JobDev& j, int M, const RunView<MT>& view, int64_t tbase,
@@ -581,16 +581,24 @@ __device__ __forceinline__ void range_stats(const JobDev& j, int M, const RunVie
     const int lane = lane_id();
     const int sf = (int)(((int64_t)first - tbase) >> 8), sl = (int)(((int64_t)last - tbase) >> 8);
     const int64_t S_all = (int64_t)uni(j.n_tiles) * uni(j.tile_steps);
+    // end steps that the range covers whole are taken from their statistics
+    const bool starts = ((int64_t)first - tbase) % kStepCells == 0;
+    const bool ends = ((int64_t)last - tbase) % kStepCells == kStepCells - 1;
+    const bool head_whole = starts && (sl > sf || ends);
+    const bool tail_whole = ends && (sl > sf || starts);
+    const int a0 = head_whole ? sf : sf + 1;          // whole steps [a0, a1)
+    const int a1 = tail_whole ? sl + 1 : sl;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         sum[m] = 0.0;
         mn[m] = INFINITY;
         mx[m] = -INFINITY;
     }
-    // the lane's 4 cells of the first step, then of the last step
+    // the lane's 4 cells of a partial first step, then of a partial last step
 #pragma unroll
     for (int end = 0; end < 2; ++end) {
-        if (end == 1 && sl == sf) break;
+        if (end == 0 && head_whole) continue;
+        if (end == 1 && (sl == sf || tail_whole)) break;
         const int st = end == 0 ? sf : sl;
         const int64_t c = tbase + (int64_t)st * kStepCells + 4 * lane;
 #pragma unroll
@@ -610,9 +618,9 @@ __device__ __forceinline__ void range_stats(const JobDev& j, int M, const RunVie
             }
         }
     }
-    // whole steps strictly between
-    if (sf + 1 + lane < sl) {
-        const int64_t gs = step0 + sf + 1 + lane;
+    // whole steps
+    if (a0 + lane < a1) {
+        const int64_t gs = step0 + a0 + lane;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             if (m < M) {
@@ -818,6 +826,37 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
         const float B = wave_incl_max(wave_incl_sum(tl));
         const float Bex = shfl_up1(B, 0.0f);
         const float stot = readlane(B, kWave - 1);
+        const bool full = c0 + kStepCells <= n;
+
+        // first bin of the step's first cell and last bin of its last cell,
+        // from lanes 0 and 63 alone (the same expressions the per-cell bins
+        // below evaluate): most steps lie inside one bin and stop here
+        const float x_first = fminf(fmaf(run + fminf(0.0f, readlane(B, 0)), scale_f, X0), X1);
+        const int key0 = max(0, min((int)floorf(x_first), W1));
+        if (s == 0) Bh = key0;
+        int key_end = INT_MAX;
+        if (full) {
+            const float B63 = readlane(B, kWave - 1);
+            const float x3 = fminf(fmaf(run + fminf(readlane(Bex, kWave - 1) + readlane(p3, kWave - 1), B63),
+                                        scale_f, X0), X1);
+            const float x4 = (uint32_t)(c0 + kStepCells - 1) == last_valid ? X1
+                                                                          : fminf(fmaf(run + B63, scale_f, X0), X1);
+            const int lo3 = max(0, min((int)floorf(x3), W1));
+            key_end = max(lo3, min((int)ceilf(x4) - 1, W1));
+        }
+        if (full && key0 == key_end && (!o_valid || key0 == O)) {
+            // the whole step lies in the open bin
+            if (!o_valid) {
+                o_valid = true;
+                O = key0;
+                O_first = (uint32_t)c0;
+            }
+            run = run + stot;
+            cur = nx1;
+            nx1 = nxt;
+            continue;
+        }
+
         float xs[5];
         xs[0] = fminf(fmaf(run + fminf(Bex, B), scale_f, X0), X1);
         xs[1] = fminf(fmaf(run + fminf(Bex + p1, B), scale_f, X0), X1);
@@ -833,23 +872,6 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
             const float en = (g[k] == last_valid) ? X1 : xs[k + 1];
             blo[k] = max(0, min((int)floorf(xs[k]), W1));
             bhi[k] = max(blo[k], min((int)ceilf(en) - 1, W1));
-        }
-
-        const bool full = c0 + kStepCells <= n;
-        const int key0 = readlane(blo[0], 0);
-        if (s == 0) Bh = key0;
-        const int key_end = full ? readlane(bhi[3], kWave - 1) : INT_MAX;
-
-        if (full && key0 == key_end && (!o_valid || key0 == O)) {
-            // the whole step lies in the open bin
-            if (!o_valid) {
-                o_valid = true;
-                O = key0;
-                O_first = (uint32_t)c0;
-            }
-            cur = nx1;
-            nx1 = nxt;
-            continue;
         }
 
         // ---- bin boundary inside the step ----
