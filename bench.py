@@ -176,7 +176,9 @@ def bench_batch32(args, dt):
     ms_graph = timed(graph, "captured graph")
     cached = all(V.entry_cache_info() is not None for V in vols)
     elem = 4 if args.dtype == "f32" else 2
-    bpc = (M + 1) if cached else (M * elem + 1)
+    segs = [V.level_segments() for V in vols]
+    lbpc = sum(nm * 64 + (ns // 4) * 4 for ns, nm in segs) / cells   # level codes + mixed segments
+    bpc = (M + lbpc) if cached else (M * elem + lbpc)
     achieved = cells * bpc / (per_launch["tile_sums"] * 1e-3) / 1e9
     ms_best = min(ms_batch, ms_graph)
     out = {
@@ -308,7 +310,6 @@ def main():
     # default: from the second update with unchanged windows on, the importance
     # pass reads the cached TF entries (one byte per cell and field).
     elem = 4 if args.dtype == "f32" else 2
-    value_bpc = M * elem + 1
     ms_values, per_launch_values, _ = measure(dvl.ENTRY_CACHE_NEVER)
     if args.entry_cache == "never":
         ms_per_step, per_launch, cached = ms_values, per_launch_values, False
@@ -316,10 +317,15 @@ def main():
         ms_per_step, per_launch, cached = measure(dvl.ENTRY_CACHE_AUTO)
 
     # roofline of the dominant kernel (the importance pass): it streams every
-    # cell's level and its M field values (or M cached entries) once.  The
-    # projection pass re-reads the values of the tiles that contain a bin
-    # edge only (at most min(tiles, W) of them).
-    bytes_per_cell = (M + 1) if cached else value_bpc
+    # cell's M field values (or M cached entries) once, plus one 32-bit level
+    # code per 256 cells and the level bytes of the 64-cell segments whose
+    # levels differ (a uniform segment's level is its code).  The projection
+    # pass re-reads the values of the tiles that contain a bin edge only (at
+    # most min(tiles, W) of them).
+    n_seg, n_mixed = V.level_segments()
+    level_bytes = n_mixed * 64 + (n_seg // 4) * 4
+    value_bpc = M * elem + level_bytes / n
+    bytes_per_cell = (M + level_bytes / n) if cached else value_bpc
     alg_bytes = n * bytes_per_cell
     dom = max(("tile_sums", "bin"), key=lambda k: per_launch[k])
     achieved = alg_bytes / (per_launch[dom] * 1e-3) / 1e9
@@ -352,6 +358,8 @@ def main():
                      "bytes_per_launch": alg_bytes, "bytes_per_cell": bytes_per_cell,
                      "avg_launch_ms": per_launch[dom]},
         "entry_cache": cached,
+        "level_segments": {"segments_of_64_cells": n_seg, "mixed": n_mixed,
+                           "level_bytes_per_cell": level_bytes / n},
         "no_entry_cache": {"ms_per_step": ms_values, "value": n / (ms_values * 1e-3),
                            "tile_sums_ms": per_launch_values["tile_sums"], "tile_sums_gbps": values_gbps,
                            "tile_sums_frac": values_gbps / HBM_PEAK_GBPS, "bytes_per_cell": value_bpc,

@@ -301,6 +301,13 @@ int32_t dvl_grid_bits(const dvl_volume* v);
 int32_t dvl_dtype(const dvl_volume* v);
 /* device bytes held by the volume (buffers and current workspace) */
 size_t dvl_volume_bytes(const dvl_volume* v);
+/* Level segments of the sorted order: the padded cells split into segments
+ * of 64 (*n_segments of them); a segment whose cells share one level is
+ * uniform, the others (*n_mixed) hold mixed levels.  The update passes read
+ * the level bytes of mixed segments only (plus one 32-bit code per 256 cells)
+ * and take the level of a uniform segment from its code.  Either pointer may
+ * be NULL.  Copies the codes to the host (synchronises the device). */
+dvl_status dvl_level_segments(const dvl_volume* v, int64_t* n_segments, int64_t* n_mixed);
 /* device workspace one update of this shape needs beyond the volume */
 size_t dvl_update_workspace_bytes(int64_t n_cells, int32_t n_fields, int32_t n_bins);
 

@@ -107,6 +107,7 @@ struct dvl_volume {
     int device = 0;
     int n_cu = 256;
     uint8_t* level_s = nullptr;
+    uint32_t* lcode_s = nullptr;      // per-step level codes [n_pad / 256]
     void* fields_s[kMaxFields] = {};
     uint64_t* keys_s = nullptr;
     uint32_t* perm = nullptr;
@@ -374,6 +375,7 @@ static dvl_status plan_batch(std::vector<ReqHost>&& reqs, Plan& P) {
         j.req0 = (int)i;
         j.tile_steps = v->tile_steps;
         j.level = v->level_s;
+        j.lcode = v->lcode_s;
         for (int m = 0; m < v->M; ++m) j.fields[m] = v->fields_s[m];
         j.agg_sum = v->agg_sum;
         j.agg_min = v->agg_min;
@@ -926,6 +928,14 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
     if (dvl_status st = launch_gather(n, v->perm, level, lv.p, 1, s)) return st;
     v->level_s = (uint8_t*)lv.release();
     v->bytes += (size_t)v->n_pad;
+    {
+        DevBuf lc;
+        const int64_t n_steps = v->n_pad / kStepCells;
+        if (dvl_status st = lc.alloc((size_t)n_steps * 4, "level codes")) return st;
+        if (dvl_status st = launch_level_codes(v->level_s, n_steps, (uint32_t*)lc.p, s)) return st;
+        v->lcode_s = (uint32_t*)lc.release();
+        v->bytes += (size_t)n_steps * 4;
+    }
     DevBuf rng;
     if (dvl_status st = rng.alloc((size_t)kMaxFields * 4 * sizeof(unsigned int), "ranges")) return st;
     std::vector<unsigned int> rinit(kMaxFields * 4, 0u);
@@ -1153,11 +1163,27 @@ int32_t dvl_grid_bits(const dvl_volume* v) { return v ? v->bits : 0; }
 int32_t dvl_dtype(const dvl_volume* v) { return v ? v->dtype : -1; }
 size_t dvl_volume_bytes(const dvl_volume* v) { return v ? v->bytes + (v->ex ? v->ex->bytes : 0) : 0; }
 
+dvl_status dvl_level_segments(const dvl_volume* v, int64_t* n_segments, int64_t* n_mixed) {
+    g_err.clear();
+    if (dvl_status st = check_volume(v)) return st;
+    const int64_t n_steps = v->n_pad / kStepCells;
+    std::vector<uint32_t> codes((size_t)n_steps);
+    DVL_HIP(hipDeviceSynchronize());
+    DVL_HIP(hipMemcpy(codes.data(), v->lcode_s, (size_t)n_steps * 4, hipMemcpyDeviceToHost));
+    int64_t mixed = 0;
+    for (uint32_t c : codes)
+        for (int k = 0; k < 4; ++k) mixed += ((c >> (8 * k)) & 0xFFu) == 0xFFu;
+    if (n_segments) *n_segments = n_steps * 4;
+    if (n_mixed) *n_mixed = mixed;
+    return DVL_OK;
+}
+
 void dvl_destroy(dvl_volume* v) {
     if (!v) return;
     (void)hipDeviceSynchronize();
     delete v->ex;
     if (v->level_s) (void)hipFree(v->level_s);
+    if (v->lcode_s) (void)hipFree(v->lcode_s);
     for (int m = 0; m < kMaxFields; ++m)
         if (v->fields_s[m]) (void)hipFree(v->fields_s[m]);
     if (v->keys_s) (void)hipFree(v->keys_s);

@@ -185,6 +185,34 @@ __device__ __forceinline__ T gload_at(const char* base, uint32_t byte_off) {
     return *(const DVL_GLOBAL T*)(g + byte_off);
 }
 
+// Read-only words at a wave-uniform address, through the constant address
+// space: scalar loads, counted apart from the vector loads in flight.  Only
+// for buffers that no kernel writes while the reading kernel runs.
+#define DVL_CONST __attribute__((address_space(4)))
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T sload(const void* base, int64_t i) {
+    return ((const DVL_CONST T*)base)[i];
+}
+
+// Work-item and work-group indices from the hardware and the dispatch packet.
+// The kernels of the update run in non-IEEE float mode, which keeps the
+// device library's functions from being inlined into them; an out-of-line
+// call waits for every memory operation in flight on entry, so the hot
+// kernels use these instead of threadIdx / blockIdx / blockDim / gridDim.
+__device__ __forceinline__ int thread_x() { return (int)__builtin_amdgcn_workitem_id_x(); }
+__device__ __forceinline__ int block_x() { return (int)__builtin_amdgcn_workgroup_id_x(); }
+__device__ __forceinline__ int block_dim_x() {
+    const DVL_CONST uint16_t* pk = (const DVL_CONST uint16_t*)__builtin_amdgcn_dispatch_ptr();
+    return (int)pk[2];                        // workgroup_size_x
+}
+__device__ __forceinline__ int grid_dim_x() {
+    const DVL_CONST uint32_t* pk = (const DVL_CONST uint32_t*)__builtin_amdgcn_dispatch_ptr();
+    const uint32_t wg = (uint32_t)block_dim_x();
+    return (int)((pk[3] + wg - 1) / wg);      // grid_size_x in work-items
+}
+
 // Values that are the same in every lane (descriptor fields) moved to scalar
 // registers, so that branches on them are scalar branches and addresses built
 // from them use scalar bases.

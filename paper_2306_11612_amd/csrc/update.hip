@@ -134,7 +134,7 @@ __device__ void carry_scan(const ReqDev& q, int64_t T, int64_t n_cells) {
     __shared__ Acc wave_acc[kCarryWaves];
     __shared__ Acc round_acc;
     __shared__ double round_end;
-    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const int tid = thread_x(), lane = lane_id(), w = tid / kWave;
     const double* ts = q.ws.run_total;
     double* base_out = q.ws.run_base;
     if (tid == 0) {
@@ -207,7 +207,7 @@ __device__ void carry_scan(const ReqDev& q, int64_t T, int64_t n_cells) {
 }
 
 __global__ __launch_bounds__(kCarryThreads) void k_carry(BatchDev b) {
-    const ReqDev& q = b.reqs[blockIdx.x];
+    const ReqDev& q = b.reqs[block_x()];
     const JobDev& j = b.jobs[q.job];
     if (q.scan_mode == DVL_SCAN_KAHAN_FP32)
         carry_scan<AccKahan32>(q, j.n_runs, j.n);
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(BatchDev b) {
 // read (the projection is hierarchical over tiles).  Other tiles are queued
 // for K3b, one wave-aggregated atomic per wave.
 __global__ __launch_bounds__(256) void k_classify(BatchDev bd) {
-    const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t u = (int64_t)block_x() * 256 + thread_x();
     bool need = false;
     int path = 0;
     if (u < bd.k3_units) {
@@ -292,7 +292,7 @@ __device__ __forceinline__ int64_t wave_partition_point(int64_t T, Pred pred) {
 template <int MT>
 __global__ __launch_bounds__(256) void k_edges(BatchDev bd) {
     const int lane = lane_id();
-    const int64_t u = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    const int64_t u = (int64_t)block_x() * (256 / kWave) + thread_x() / kWave;
     if (u >= bd.k4_units) return;
     const int qi = find_req_k4(bd, u);
     const ReqDev& q = bd.reqs[qi];
@@ -385,8 +385,8 @@ __global__ __launch_bounds__(kUpdThreads) void k_tile_aggregates(int64_t n, cons
                                                                  double* __restrict__ ssum,
                                                                  float* __restrict__ smn, float* __restrict__ smx) {
     const int lane = lane_id();
-    const int64_t wave = (int64_t)blockIdx.x * (kUpdThreads / kWave) + threadIdx.x / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * (kUpdThreads / kWave);
+    const int64_t wave = (int64_t)block_x() * (kUpdThreads / kWave) + thread_x() / kWave;
+    const int64_t nwaves = (int64_t)grid_dim_x() * (kUpdThreads / kWave);
     for (int64_t t = wave; t < n_tiles; t += nwaves) {
         const int64_t tbase = t * tile_steps * (int64_t)kStepCells;
         double acc = 0.0;
@@ -450,14 +450,48 @@ dvl_status launch_tile_aggregates(int64_t n, int dtype, const void* field, int64
     return DVL_OK;
 }
 
+// ------------------------------------------------------------------ level codes
+
+// One 32-bit code per 256-cell step of the sorted levels: byte k describes
+// the cells [64 k, 64 k + 64) of the step (the 16 lanes 16 k .. 16 k + 15 of
+// a wave reading the step): their common level, or 0xFF when they differ.
+// One wave per step.
+__global__ __launch_bounds__(256) void k_level_codes(const uint32_t* __restrict__ lev4, int64_t n_steps,
+                                                     uint32_t* __restrict__ codes) {
+    const int64_t st = ((int64_t)block_x() * block_dim_x() + thread_x()) / kWave;
+    if (st >= n_steps) return;   // the whole wave
+    const int lane = lane_id();
+    const uint32_t w = lev4[st * kWave + lane];
+    const uint32_t b0 = w & 0xFFu;
+    const uint32_t c = w == b0 * 0x01010101u ? b0 : 0xFFu;
+    uint32_t lo = c, hi = c;
+    for (int o = 1; o < 16; o <<= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, o));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, o));
+    }
+    const uint32_t seg = lo == hi ? lo : 0xFFu;
+    const uint32_t s0 = (uint32_t)__shfl((int)seg, 0), s1 = (uint32_t)__shfl((int)seg, 16);
+    const uint32_t s2 = (uint32_t)__shfl((int)seg, 32), s3 = (uint32_t)__shfl((int)seg, 48);
+    if (lane == 0) codes[st] = s0 | (s1 << 8) | (s2 << 16) | (s3 << 24);
+}
+
+dvl_status launch_level_codes(const uint8_t* level, int64_t n_steps, uint32_t* codes, hipStream_t s) {
+    const int64_t threads = n_steps * kWave;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, (threads + 255) / 256);
+    hipLaunchKernelGGL(k_level_codes, dim3(grid), dim3(256), 0, s, reinterpret_cast<const uint32_t*>(level),
+                       n_steps, codes);
+    DVL_HIP(hipGetLastError());
+    return DVL_OK;
+}
+
 // ------------------------------------------------------------------ TF entry cache
 
 // entries of 4 consecutive cells per lane, packed into one 32-bit store
 template <typename S>
 __global__ __launch_bounds__(256) void k_build_index(int64_t n_quads, const void* __restrict__ field, float s,
                                                      float b, float nmax, uint32_t* __restrict__ out) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_quads; i += stride) {
+    const int64_t stride = (int64_t)grid_dim_x() * block_dim_x();
+    for (int64_t i = (int64_t)block_x() * block_dim_x() + thread_x(); i < n_quads; i += stride) {
         Quad<S> q;
         q.load(field, i);
         uint32_t w = 0;

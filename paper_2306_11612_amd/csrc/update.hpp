@@ -93,6 +93,7 @@ struct JobDev {
     int tile_steps;           // 256-cell steps per tile
     int pad_;
     const uint8_t* level;
+    const uint32_t* lcode;    // per-step level codes (launch_level_codes)
     const void* fields[kMaxFields];
     const uint8_t* idx[kMaxFields];   // cached TF entries per field, or all NULL: read the values
     const double* agg_sum;    // per-tile field statistics [M][T]
@@ -131,6 +132,11 @@ dvl_status launch_batch(const BatchDev& b, int dtype, int max_m, int max_req, in
 // n_tf <= 256 entries, one byte per cell, over all n_pad (padded) cells.
 dvl_status launch_build_index(int64_t n_pad, int dtype, const void* field, float s, float b, int n_tf,
                               uint8_t* out, int n_cu, hipStream_t st);
+
+// Level codes of the sorted levels (n_steps * 256 bytes, padded): per
+// 256-cell step one 32-bit word whose byte k is the common level of the cells
+// [64 k, 64 k + 64) of the step, or 0xFF when they differ.
+dvl_status launch_level_codes(const uint8_t* level, int64_t n_steps, uint32_t* codes, hipStream_t s);
 
 // Per-tile and per-step (256 cells) sum / min / max of one sorted field:
 // tile arrays [n_tiles], step arrays [n_tiles * tile_steps].

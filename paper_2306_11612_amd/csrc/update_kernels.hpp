@@ -92,7 +92,7 @@ __device__ __forceinline__ float variation(const float (&x)[MT], int M, const fl
 // Eq. 3 with the minimum importance
 __device__ __forceinline__ float importance_from_v(float v, uint32_t L, const ImpCtx& c) {
     const float r = v * c.inv_vmax;
-    const int e = (int)__umul24((uint32_t)c.lshift, L);
+    const int e = (int)(((uint32_t)c.lshift & 0xFFu) * (L & 0xFFu));   // 8 x 8 bits: a 24-bit multiply
     float f;
     if (c.clamp_mode == 0) {
         const float g = ldexpf(r, e);
@@ -111,7 +111,7 @@ __device__ __forceinline__ float importance_from_v(float v, uint32_t L, const Im
 // the same operations as importance_from_v takes for it
 __device__ __forceinline__ float importance_p1(float v, uint32_t L, const ImpCtx& c) {
     const float r = v * c.inv_vmax;
-    const int e = (int)__umul24((uint32_t)c.lshift, L);
+    const int e = (int)(((uint32_t)c.lshift & 0xFFu) * (L & 0xFFu));   // 8 x 8 bits: a 24-bit multiply
     return fmaxf(ldexpf(r, e), c.fmin);
 }
 
@@ -122,11 +122,27 @@ __device__ __forceinline__ int fields_of(int M) {
 
 // A wave's streams over one run of a job: scalar base pointers advanced to
 // the run's first cell, so every load is a scalar base plus a 32-bit lane
-// offset (a run holds at most 1/64 of a volume, well below 2^32 bytes).
+// offset (a run holds at most 1/64 of a volume, well below 2^32 bytes), and
+// the level codes of the run's steps.
 template <int MT>
 struct RunView {
     const char* base[MT];
     const char* lev;
+    const uint32_t* lcode;
+};
+
+// Levels of the 4 cells of a lane.  The per-step level code says for every
+// 64 cells whether they share one level; lanes in such a segment take it from
+// the code and point their level load at the run's first word (a cached
+// line), so only segments of mixed levels fetch level bytes.
+struct LaneLevels {
+    uint32_t lv;   // loaded levels (meaningful for code 0xFF only)
+    uint32_t lc;   // the lane's segment code
+    __device__ __forceinline__ void load(const char* lev, uint32_t qd, uint32_t code) {
+        lc = (code >> ((lane_id() >> 4) << 3)) & 0xFFu;
+        lv = gload_at<uint32_t>(lev, lc == 0xFFu ? qd * 4u : 0u);
+    }
+    __device__ __forceinline__ uint32_t get(int k) const { return lc == 0xFFu ? (lv >> (8 * k)) & 0xFFu : lc; }
 };
 
 // values of the 4 cells of this lane in the given step
@@ -134,20 +150,15 @@ template <int MT, typename S>
 struct StepData {
     static constexpr uint32_t kQuadBytes = Quad<S>::kBytes;
     Quad<S> q[MT];
-    uint32_t lv;
-    __device__ __forceinline__ void load(const JobDev& j, int M, int64_t quad) {
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-            if (m < M) q[m].load(j.fields[m], quad);
-        lv = gload<uint32_t>(j.level, quad);
-    }
+    LaneLevels lv;
     __device__ static const void* source(const JobDev& j, int m) { return j.fields[m]; }
-    // qd: quad index from the run's first cell
-    __device__ __forceinline__ void load(const RunView<MT>& v, int M, uint32_t qd) {
+    // step: index from the run's first step; code: its level code
+    __device__ __forceinline__ void load(const RunView<MT>& v, int M, int step, uint32_t code) {
+        const uint32_t qd = (uint32_t)(step * kWave + lane_id());
 #pragma unroll
         for (int m = 0; m < MT; ++m)
             if (m < M) q[m].load_at(v.base[m], qd * kQuadBytes);
-        lv = gload_at<uint32_t>(v.lev, qd * 4u);
+        lv.load(v.lev, qd, code);
     }
 };
 
@@ -157,13 +168,14 @@ template <int MT>
 struct StepIdx {
     static constexpr uint32_t kQuadBytes = 4;
     uint32_t e[MT];
-    uint32_t lv;
+    LaneLevels lv;
     __device__ static const void* source(const JobDev& j, int m) { return j.idx[m]; }
-    __device__ __forceinline__ void load(const RunView<MT>& v, int M, uint32_t qd) {
+    __device__ __forceinline__ void load(const RunView<MT>& v, int M, int step, uint32_t code) {
+        const uint32_t qd = (uint32_t)(step * kWave + lane_id());
 #pragma unroll
         for (int m = 0; m < MT; ++m)
             if (m < M) e[m] = gload_at<uint32_t>(v.base[m], qd * 4u);
-        lv = gload_at<uint32_t>(v.lev, qd * 4u);
+        lv.load(v.lev, qd, code);
     }
 };
 
@@ -173,9 +185,8 @@ template <int MT>
 struct StepF {
     static constexpr uint32_t kQuadBytes = 16;
     f32x4 fv;
-    uint32_t lv;
-    __device__ __forceinline__ void load(const RunView<MT>& v, int M, uint32_t qd) {
-        fv = gload_at<f32x4>(v.base[0], qd * kQuadBytes);
+    __device__ __forceinline__ void load(const RunView<MT>& v, int M, int step, uint32_t code) {
+        fv = gload_at<f32x4>(v.base[0], (uint32_t)(step * kWave + lane_id()) * kQuadBytes);
     }
 };
 
@@ -187,6 +198,7 @@ __device__ __forceinline__ RunView<MT> run_view(const JobDev& j, int M, int64_t 
     for (int m = 0; m < MT; ++m)
         v.base[m] = m < M ? uni(reinterpret_cast<const char*>(D::source(j, m))) + quad0 * D::kQuadBytes : nullptr;
     v.lev = uni(reinterpret_cast<const char*>(j.level)) + quad0 * 4;
+    v.lcode = uni(j.lcode) + (c_begin >> 8);
     return v;
 }
 
@@ -237,6 +249,30 @@ __device__ __forceinline__ void table_offsets(const ReqDev& q, int M, int (&off)
 template <typename D> struct Group { static constexpr int n = 1; };
 template <int MT> struct Group<StepIdx<MT>> { static constexpr int n = 4; };
 
+// level codes of the G steps of a group (step: its first, a multiple of G).
+// Groups of 4 steps (cached entries) fetch theirs through a vector load
+// (every lane the same words), waited for in order with the stream loads;
+// single steps (values, whose registers are scarcer) through a scalar load.
+template <int G>
+struct StepCodes {
+    uint32_t c[G];
+};
+template <int G>
+__device__ __forceinline__ StepCodes<G> load_codes(const uint32_t* lcode, int step) {
+    StepCodes<G> r;
+    if constexpr (G == 4) {
+        const u32x4 w = gload<u32x4>(lcode + step, 0);
+        r.c[0] = w.x;
+        r.c[1] = w.y;
+        r.c[2] = w.z;
+        r.c[3] = w.w;
+    } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g) r.c[g] = sload<uint32_t>(lcode, step + g);
+    }
+    return r;
+}
+
 // ------------------------------------------------------------------ K0
 
 template <int MT, int KR, typename D>
@@ -264,7 +300,7 @@ __device__ __forceinline__ void vmax_run(const BatchDev& b, const JobDev& j, int
     for (int s = 0; s < nsteps; s += G) {
         D d[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) d[g].load(view, M, (uint32_t)((s + g) * kWave + lane));
+        for (int g = 0; g < G; ++g) d[g].load(view, M, s + g, 0u);   // levels unused
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (s + g >= nsteps) break;
@@ -300,14 +336,14 @@ __device__ __forceinline__ void load_job_tables(const BatchDev& b, const JobDev&
         if constexpr (IDX) {
             const int M = uni(fields_of<MT>(j.M)), nq = uni(j.n_req);
             const ReqDev* rq = b.reqs + uni(j.req0);
-            for (int i = threadIdx.x; i < nq * MT * kIdxTable; i += blockDim.x) {
+            for (int i = thread_x(); i < nq * MT * kIdxTable; i += block_dim_x()) {
                 const int q = i / (MT * kIdxTable), m = (i / kIdxTable) % MT, e = i % kIdxTable;
                 float v = 0.0f;
                 if (m < M && e < (int)rq[q].nmax[m] + 1) v = gload<float>(rq[q].tf, rq[q].tf_off[m] + e);
                 tf_lds[i] = v;
             }
         } else {
-            for (int i = threadIdx.x; i < j.tf_total_all; i += blockDim.x) tf_lds[i] = gload<float>(j.tf_all, i);
+            for (int i = thread_x(); i < j.tf_total_all; i += block_dim_x()) tf_lds[i] = gload<float>(j.tf_all, i);
         }
         __syncthreads();
         loaded = ji;
@@ -318,9 +354,9 @@ __device__ __forceinline__ void load_job_tables(const BatchDev& b, const JobDev&
 template <int MT, typename S, int KR, int IDX>
 __global__ __launch_bounds__(kUpdThreads) void k_vmax_exact(BatchDev b) {
     extern __shared__ float tf_lds[];
-    const int wv = uni((int)(threadIdx.x / kWave));
+    const int wv = uni((int)(thread_x() / kWave));
     int loaded = -1;
-    for (int64_t u = blockIdx.x; u < b.k1_units; u += gridDim.x) {
+    for (int64_t u = block_x(); u < b.k1_units; u += grid_dim_x()) {
         const int ji = find_job_k1(b, u);
         const JobDev& j = b.jobs[ji];
         if ((j.idx[0] != nullptr) != (IDX != 0)) continue;
@@ -384,16 +420,24 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
     ImpCtx ctx[KR];
     RunAcc run[KR];
     double prev[KR], tacc[KR];
-    int toff[KR], off[KR][MT];
+    int toff[KR], off[KR][MT], mode[KR];
     float* fst[KR];                   // where f of every cell is kept for the projection, or NULL
+    double* lpre[KR];                 // the requests' in-run tile prefixes
+    // every descriptor field the loop reads is held in registers: a load
+    // inside the loop would be the youngest in flight, and waiting for it
+    // would drain the prefetched steps
 #pragma unroll
     for (int q = 0; q < KR; ++q) {
         fst[q] = nullptr;
+        lpre[q] = nullptr;
+        mode[q] = DVL_SCAN_FP64;
         if (q < nreq) {
             ctx[q] = make_ctx(rq[q]);
             toff[q] = uni(rq[q].tf_job_off);
             table_offsets<MT>(rq[q], M, off[q]);
             fst[q] = uni(rq[q].ws.fstore);
+            lpre[q] = uni(rq[q].ws.local_prefix);
+            mode[q] = uni(rq[q].scan_mode);
         }
         run[q].init();
         prev[q] = 0.0;
@@ -402,16 +446,10 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
     int64_t t = t_begin;
     int in_tile = 0;
     const RunView<MT> view = run_view<MT, D>(j, M, c_begin);
-    D cur[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) cur[g].load(view, M, (uint32_t)(g * kWave + lane));
-    for (int s = 0; s < nsteps; s += G) {
-        // the next group, unconditionally (the last group reloads the last
-        // step): a conditional load would make the compiler wait for all
-        // outstanding loads before using the current group
-        D nxt[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) nxt[g].load(view, M, (uint32_t)(min(s + G + g, nsteps - 1) * kWave + lane));
+    const int last_group = (nsteps - 1) / G * G;
+
+    // the steps s .. s + G - 1 of the run, loaded into `cur`
+    auto process = [&](const D (&cur)[G], int s) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (s + g >= nsteps) break;
@@ -424,7 +462,7 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const float v = cell_v<MT>(cur[g], k, M, tf_lds + TableBase<MT, D>::of(q, toff[q]), rq[q], off[q]);
-                        const uint32_t L = (cur[g].lv >> (8 * k)) & 0xFFu;
+                        const uint32_t L = cur[g].lv.get(k);
                         f[k] = P1 ? importance_p1(v, L, ctx[q]) : importance_from_v(v, L, ctx[q]);
                     }
                     if (!full) {
@@ -446,24 +484,57 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
 #pragma unroll
                 for (int q = 0; q < KR; ++q) {
                     if (q < nreq) {
-                        const int mode = rq[q].scan_mode;
                         const double ts = wave_sum_d(tacc[q]);
                         tacc[q] = 0.0;
-                        prev[q] = fmax(prev[q], run[q].value(mode));
-                        if (lane == 0) gstore<double>(rq[q].ws.local_prefix, t, prev[q]);
-                        run[q].add(mode, ts);
+                        prev[q] = fmax(prev[q], run[q].value(mode[q]));
+                        if (lane == 0) gstore<double>(lpre[q], t, prev[q]);
+                        run[q].add(mode[q], ts);
                     }
                 }
                 ++t;
                 in_tile = 0;
             }
         }
+    };
+
+    // Two groups in flight, in buffers A and B that take turns: a buffer is
+    // loaded again (unconditionally; past the run's end the last step is
+    // reloaded) right after its group was used, so no loaded value is ever
+    // moved and every wait is for the older of the two groups only.  The
+    // level codes a reload needs were fetched before the buffer's previous
+    // load, so they have arrived.
+    D A[G], B[G];
+    StepCodes<G> cA, cB;
+    {
+        const StepCodes<G> c0 = load_codes<G>(view.lcode, 0);
+        const StepCodes<G> c1 = load_codes<G>(view.lcode, min(G, last_group));
+        cA = load_codes<G>(view.lcode, min(2 * G, last_group));
 #pragma unroll
-        for (int g = 0; g < G; ++g) cur[g] = nxt[g];
+        for (int g = 0; g < G; ++g) A[g].load(view, M, g, c0.c[g]);
+        cB = load_codes<G>(view.lcode, min(3 * G, last_group));
+#pragma unroll
+        for (int g = 0; g < G; ++g) B[g].load(view, M, min(G + g, nsteps - 1), c1.c[g]);
+    }
+    for (int s = 0; s < nsteps; s += 2 * G) {
+        process(A, s);
+        {
+            const StepCodes<G> c2 = load_codes<G>(view.lcode, min(s + 4 * G, last_group));
+#pragma unroll
+            for (int g = 0; g < G; ++g) A[g].load(view, M, min(s + 2 * G + g, nsteps - 1), cA.c[g]);
+            cA = c2;
+        }
+        if (s + G >= nsteps) break;
+        process(B, s + G);
+        {
+            const StepCodes<G> c3 = load_codes<G>(view.lcode, min(s + 5 * G, last_group));
+#pragma unroll
+            for (int g = 0; g < G; ++g) B[g].load(view, M, min(s + 3 * G + g, nsteps - 1), cB.c[g]);
+            cB = c3;
+        }
     }
 #pragma unroll
     for (int q = 0; q < KR; ++q)
-        if (q < nreq && lane == 0) gstore<double>(rq[q].ws.run_total, r, fmax(prev[q], run[q].value(rq[q].scan_mode)));
+        if (q < nreq && lane == 0) gstore<double>(rq[q].ws.run_total, r, fmax(prev[q], run[q].value(mode[q])));
 }
 
 // A workgroup takes 4 consecutive runs of one job; wave r of the job owns the
@@ -471,9 +542,9 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
 template <int MT, typename S, int KR, int IDX>
 __global__ __launch_bounds__(kUpdThreads) void k_tile_sums(BatchDev b) {
     extern __shared__ float tf_lds[];
-    const int wv = uni((int)(threadIdx.x / kWave));
+    const int wv = uni((int)(thread_x() / kWave));
     int loaded = -1;
-    for (int64_t u = blockIdx.x; u < b.k1_units; u += gridDim.x) {
+    for (int64_t u = block_x(); u < b.k1_units; u += grid_dim_x()) {
         const int ji = find_job_k1(b, u);
         const JobDev& j = b.jobs[ji];
         if ((j.idx[0] != nullptr) != (IDX != 0)) continue;
@@ -794,13 +865,15 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
     uint32_t O_first = 0;
 
     D cur, nx1;
-    cur.load(view, M, (uint32_t)lane);
-    nx1.load(view, M, (uint32_t)(min(1, nsteps - 1) * kWave + lane));
+    cur.load(view, M, 0, sload<uint32_t>(view.lcode, 0));
+    nx1.load(view, M, min(1, nsteps - 1), sload<uint32_t>(view.lcode, min(1, nsteps - 1)));
+    uint32_t code2 = sload<uint32_t>(view.lcode, min(2, nsteps - 1));
     for (int s = 0; s < nsteps; ++s) {
         const int64_t c0 = tbase + (int64_t)s * kStepCells;
         const int64_t quad = (c0 >> 2) + lane;
         D nxt;
-        nxt.load(view, M, (uint32_t)(min(s + 2, nsteps - 1) * kWave + lane));
+        nxt.load(view, M, min(s + 2, nsteps - 1), code2);
+        const uint32_t code3 = sload<uint32_t>(view.lcode, min(s + 3, nsteps - 1));
 
         float f[4];
         uint32_t g[4];
@@ -814,8 +887,7 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
                 if (!degenerate) fk = k == 0 ? cur.fv.x : (k == 1 ? cur.fv.y : (k == 2 ? cur.fv.z : cur.fv.w));
             } else {
                 if (!degenerate)
-                    fk = importance_from_v(rescan_v<MT>(cur, k, M, tf_lds, q, off), (cur.lv >> (8 * k)) & 0xFFu,
-                                           c);
+                    fk = importance_from_v(rescan_v<MT>(cur, k, M, tf_lds, q, off), cur.lv.get(k), c);
             }
             f[k] = valid[k] ? fk : 0.0f;
         }
@@ -854,6 +926,7 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
             run = run + stot;
             cur = nx1;
             nx1 = nxt;
+            code2 = code3;
             continue;
         }
 
@@ -926,6 +999,7 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
         }
         cur = nx1;
         nx1 = nxt;
+        code2 = code3;
     }
 
     // tile end: the open bin is the tile's last bin
@@ -949,7 +1023,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
     const int64_t n_queued = gload<uint32_t>(bd.rescan_count, IDX);
     const uint64_t* queue = bd.rescan_queue + IDX * bd.k3_units;
 
-    for (int64_t i = blockIdx.x; i < n_queued; i += gridDim.x) {
+    for (int64_t i = block_x(); i < n_queued; i += grid_dim_x()) {
         const int64_t u = uni((int64_t)gload<uint64_t>(queue, i));
         const int qi = uni(find_req_k3(bd, u));
         const ReqDev& q = bd.reqs[qi];

@@ -93,6 +93,7 @@ def lib():
         "dvl_grid_bits": (i32, [vp]),
         "dvl_dtype": (i32, [vp]),
         "dvl_volume_bytes": (C.c_size_t, [vp]),
+        "dvl_level_segments": (i32, [vp, vp, vp]),
         "dvl_update_workspace_bytes": (C.c_size_t, [i64, i32, i32]),
         "dvl_destroy": (None, [vp]),
         "dvl_set_entry_cache": (i32, [vp, i32]),
@@ -256,6 +257,12 @@ class Volume:
     @property
     def nbytes(self) -> int:
         return int(lib().dvl_volume_bytes(self.handle))
+
+    def level_segments(self):
+        """(segments of 64 sorted cells, segments of mixed levels): dvl_level_segments."""
+        ns, nm = C.c_int64(), C.c_int64()
+        _check(lib().dvl_level_segments(self.handle, C.byref(ns), C.byref(nm)), "dvl_level_segments")
+        return ns.value, nm.value
 
     def field_range(self, m: int):
         lo, hi = C.c_float(), C.c_float()

@@ -75,6 +75,59 @@ def test_cfg1_grid_update():
     run_case(vol, tfs(synth.SEED + 1, 4, n_cp=(4, 4)), 1024, label="cfg1")
 
 
+def _expected_level_segments(level_sorted: np.ndarray, n_pad: int):
+    lv = np.zeros(n_pad, np.uint8)
+    lv[: level_sorted.size] = level_sorted
+    seg = lv.reshape(-1, 64)
+    return seg.shape[0], int(np.sum(seg.min(1) != seg.max(1)))
+
+
+@pytest.mark.parametrize("seed,frac,entry_cache", [(4, 0.4, 0), (5, 0.7, 1), (6, 0.2, 2)])
+def test_level_segments_and_codes(seed, frac, entry_cache):
+    """The per-step level codes (64-cell segments of one level) against the
+    sorted levels, and an update that reads them against the oracle."""
+    vol = random_amr(seed, base=8, levels=4, frac=frac, n_fields=3)
+    D = dvl()
+    dev = vol.to("cuda")
+    V = D.build_order(dev.x, dev.y, dev.z, dev.level, dev.fields)
+    try:
+        lev, _ = V.export_sorted()
+        n_pad = -(-vol.n // 4096) * 4096
+        got = V.level_segments()
+        exp = _expected_level_segments(lev.cpu().numpy(), n_pad)
+        assert got == exp, (got, exp)
+        assert 0 < got[1] < got[0]      # both kinds present
+    finally:
+        V.close()
+    run_case(vol, tfs(seed, 3), 300, label=f"codes seed {seed}", entry_cache=entry_cache)
+    run_case(vol, tfs(seed + 1, 3), 300, level_scale=3, label=f"codes seed {seed} l3", entry_cache=entry_cache)
+
+
+def test_uniform_nonzero_level():
+    """Every cell at level 2 (a regular grid of 4-wide cells): every segment
+    of real cells is uniform with a nonzero code."""
+    import itertools
+    import synth
+    rng = np.random.default_rng(9)
+    c = np.array(list(itertools.product(range(0, 64, 4), repeat=3)), np.int32)[:3000]
+    n = c.shape[0]
+    fields = [torch.from_numpy(rng.lognormal(0, 1, n).astype(np.float32)) for _ in range(2)]
+    vol = synth.Volume(torch.from_numpy(c[:, 0].copy()), torch.from_numpy(c[:, 1].copy()),
+                       torch.from_numpy(c[:, 2].copy()), torch.full((n,), 2, dtype=torch.uint8), fields,
+                       ["a", "b"], 16, 1, [])
+    D = dvl()
+    dev = vol.to("cuda")
+    V = D.build_order(dev.x, dev.y, dev.z, dev.level, dev.fields)
+    try:
+        ns, nm = V.level_segments()
+        assert ns == 4096 // 64 and nm == (1 if n % 64 else 0)   # the segment shared with the padding
+    finally:
+        V.close()
+    for cache in (0, 1, 2):
+        run_case(vol, tfs(9, 2), 100, label="all level 2", entry_cache=cache)
+        run_case(vol, tfs(10, 2), 100, level_scale=3, exponent=2.0, label="all level 2, p=2", entry_cache=cache)
+
+
 def test_uniform_variation_is_exactly_linear():
     """TFs constant 1 and 0 give V = max V at every cell: with N = 2^18 and
     W = 2^10 every GPU operation is exact, so bin b is cells 256b..256b+255."""
