@@ -243,16 +243,19 @@ __device__ __forceinline__ void table_offsets(const ReqDev& q, int M, int (&off)
 }
 
 // How many steps one loop iteration loads ahead: one 4-vector per field is
-// enough to keep HBM busy; cached entries are a quarter of that, so four
-// steps go together (tiles hold a multiple of four steps and are padded, so
-// the loads of a group stay inside the volume's buffers).
+// enough to keep HBM busy; 16-bit values are half of that and cached entries
+// a quarter, so two or four steps go together (tiles hold a multiple of four
+// steps and are padded, so the loads of a group stay inside the volume's
+// buffers).
 template <typename D> struct Group { static constexpr int n = 1; };
 template <int MT> struct Group<StepIdx<MT>> { static constexpr int n = 4; };
+template <int MT> struct Group<StepData<MT, F16>> { static constexpr int n = 2; };
+template <int MT> struct Group<StepData<MT, BF16>> { static constexpr int n = 2; };
 
-// level codes of the G steps of a group (step: its first, a multiple of G).
-// Groups of 4 steps (cached entries) fetch theirs through a vector load
-// (every lane the same words), waited for in order with the stream loads;
-// single steps (values, whose registers are scarcer) through a scalar load.
+// level codes of the G steps of a group (step: its first, a multiple of G),
+// through vector loads (every lane the same words): they are waited for in
+// order with the stream loads (a scalar load would be waited for with the
+// LDS lookups, and all outstanding scalar loads at once)
 template <int G>
 struct StepCodes {
     uint32_t c[G];
@@ -268,7 +271,7 @@ __device__ __forceinline__ StepCodes<G> load_codes(const uint32_t* lcode, int st
         r.c[3] = w.w;
     } else {
 #pragma unroll
-        for (int g = 0; g < G; ++g) r.c[g] = sload<uint32_t>(lcode, step + g);
+        for (int g = 0; g < G; ++g) r.c[g] = gload<uint32_t>(lcode, step + g);
     }
     return r;
 }
