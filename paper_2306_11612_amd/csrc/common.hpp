@@ -185,16 +185,9 @@ __device__ __forceinline__ T gload_at(const char* base, uint32_t byte_off) {
     return *(const DVL_GLOBAL T*)(g + byte_off);
 }
 
-// Read-only words at a wave-uniform address, through the constant address
-// space: scalar loads, counted apart from the vector loads in flight.  Only
-// for buffers that no kernel writes while the reading kernel runs.
+// The constant address space (the dispatch packet is read through it).
 #define DVL_CONST __attribute__((address_space(4)))
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-__device__ __forceinline__ T sload(const void* base, int64_t i) {
-    return ((const DVL_CONST T*)base)[i];
-}
 
 // Work-item and work-group indices from the hardware and the dispatch packet.
 // The kernels of the update run in non-IEEE float mode, which keeps the

@@ -868,15 +868,20 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
     uint32_t O_first = 0;
 
     D cur, nx1;
-    cur.load(view, M, 0, sload<uint32_t>(view.lcode, 0));
-    nx1.load(view, M, min(1, nsteps - 1), sload<uint32_t>(view.lcode, min(1, nsteps - 1)));
-    uint32_t code2 = sload<uint32_t>(view.lcode, min(2, nsteps - 1));
+    // level codes through vector loads issued two steps before the loads
+    // that use them (waited for in order, ahead of the prefetched steps)
+    const uint32_t code0 = gload<uint32_t>(view.lcode, 0);
+    const uint32_t code1 = gload<uint32_t>(view.lcode, min(1, nsteps - 1));
+    uint32_t code2 = gload<uint32_t>(view.lcode, min(2, nsteps - 1));
+    uint32_t code3 = gload<uint32_t>(view.lcode, min(3, nsteps - 1));
+    cur.load(view, M, 0, code0);
+    nx1.load(view, M, min(1, nsteps - 1), code1);
     for (int s = 0; s < nsteps; ++s) {
         const int64_t c0 = tbase + (int64_t)s * kStepCells;
         const int64_t quad = (c0 >> 2) + lane;
+        const uint32_t code4 = gload<uint32_t>(view.lcode, min(s + 4, nsteps - 1));
         D nxt;
         nxt.load(view, M, min(s + 2, nsteps - 1), code2);
-        const uint32_t code3 = sload<uint32_t>(view.lcode, min(s + 3, nsteps - 1));
 
         float f[4];
         uint32_t g[4];
@@ -930,6 +935,7 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
             cur = nx1;
             nx1 = nxt;
             code2 = code3;
+            code3 = code4;
             continue;
         }
 
@@ -1003,6 +1009,7 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
         cur = nx1;
         nx1 = nxt;
         code2 = code3;
+        code3 = code4;
     }
 
     // tile end: the open bin is the tile's last bin
