@@ -101,7 +101,7 @@ dvl_status dvl_build_order(int64_t n_cells, const int32_t* x, const int32_t* y,
  *   tile_steps   cells per tile = 256 * tile_steps; 8, 16 or 32 (0: 16).  The
  *                projection reads again only tiles that contain a bin edge.
  *   run_waves    the importance pass splits the tiles into at most this many
- *                runs of consecutive tiles, one wave each (0: 16 per compute
+ *                runs of consecutive tiles, one wave each (0: 32 per compute
  *                unit); 64 <= run_waves <= 65536 otherwise.
  *   entry_cache  the TF entry of a cell (Eq. 1's lookup) depends on its value
  *                and the field's window and table size only, not on the

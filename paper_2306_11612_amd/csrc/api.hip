@@ -874,8 +874,10 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
     DVL_HIP(hipDeviceGetAttribute(&v->n_cu, hipDeviceAttributeMultiprocessorCount, v->device));
     {
         // runs of consecutive tiles, one per wave of the importance pass; the
-        // default (16 per compute unit) fits one round of resident waves
-        const int64_t waves = run_waves ? run_waves : (int64_t)v->n_cu * 16;
+        // default (32 per compute unit) is two rounds of resident waves: a
+        // wave that finishes early takes another run, which evens out the
+        // finishing times of the compute units
+        const int64_t waves = run_waves ? run_waves : (int64_t)v->n_cu * 32;
         v->tiles_per_run = std::max<int64_t>(1, (v->n_tiles + waves - 1) / waves);
         v->n_runs = (v->n_tiles + v->tiles_per_run - 1) / v->tiles_per_run;
     }

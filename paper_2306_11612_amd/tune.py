@@ -24,8 +24,8 @@ import torch
 
 from . import dvl
 
-# (tile_steps, run waves per compute unit; 0 = the library default of 16)
-CANDIDATES = [(16, 0), (8, 0), (32, 0), (16, 32), (16, 40), (8, 32), (32, 20)]
+# (tile_steps, run waves per compute unit; 0 = the library default of 32)
+CANDIDATES = [(16, 0), (8, 0), (32, 0), (16, 16), (32, 16), (8, 16), (16, 48)]
 
 
 def cache_path() -> str:
