@@ -10,7 +10,7 @@ the oracle run on
        axis, min/max bitwise, mean within 1e-5 relative);
   (ii) the original fp32 data: error of every output, reported only.
 
-    python tests/precision_study.py [--base 256] [--out gpurun_out/precision.json]
+    python tests/precision_study.py [--base 256] [--out precision_amr5_500m.json]
 
 Run on a GPU; it holds the sorted fields on the host (about 9 GB at full size)
 and runs the oracle once per distinct input (about 20-40 s each).
@@ -70,7 +70,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--base", type=int, default=256)
     ap.add_argument("--bins", type=int, default=1920)
-    ap.add_argument("--out", default="gpurun_out/precision.json")
+    ap.add_argument("--out", default="precision_amr5_500m.json")
     args = ap.parse_args()
     import synth
     from paper_2306_11612_amd import dvl
