@@ -78,26 +78,55 @@ def profiled_traffic(workload: str, dtype: str, kernel: str):
     return rec.get("traffic_bytes_per_launch", {}).get("k_" + kernel)
 
 
-def cpu_baseline(V, alphas, n_bins: int, sample: int, exponent: float, fmin: float):
-    """The oracle (single-threaded C, fp64) on the first `sample` sorted cells."""
+def host_cpu() -> dict:
+    """CPU model and logical CPU count of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def cpu_baseline(upd_inputs, alphas, n_bins: int, exponent: float, fmin: float, order_inputs=None):
+    """The oracle (single-threaded C, fp64) timed on the GPU machine's host: one
+    update over a sample of the workload's cells (`upd_inputs`: levels and
+    fields of the first cells in generation order; the oracle's cost per cell
+    does not depend on the order) and its ordering step (keys + sort) over the
+    first cells of `order_inputs` (x, y, z, level)."""
     import numpy as np
-    import torch
     import oracle
-    n = min(V.n, sample)
-    lev, fields = V.export_sorted()
-    L = lev[:n].cpu().numpy()
-    F = np.stack([f[:n].float().cpu().numpy() for f in fields])
-    del lev, fields
-    torch.cuda.empty_cache()
+    L, F = upd_inputs
+    n = L.shape[0]
     lo, hi = oracle.default_windows(F)
     hi = np.where(hi > lo, hi, np.nextafter(lo, np.float32(np.inf))).astype(np.float32)
     oracle.lib()
     t0 = time.perf_counter()
     oracle.update(L, F, alphas, lo, hi, n_bins, exponent, fmin)
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} Hilbert-sorted cells of the same volume, one update "
-                      f"(W={n_bins}), {dt:.2f} s single-threaded fp64"}
+    out = {"value": n / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {n} cells of the same volume (generation order), one update "
+                     f"(W={n_bins}), {dt:.2f} s single-threaded fp64",
+           "threads": 1, **host_cpu()}
+    if order_inputs is not None:
+        xs, ys, zs, ls = (np.ascontiguousarray(a) for a in order_inputs)
+        k = xs.shape[0]
+        bits = oracle.grid_bits(xs, ys, zs, ls)
+        t0 = time.perf_counter()
+        keys = oracle.cell_keys(xs, ys, zs, ls, bits)
+        t1 = time.perf_counter()
+        oracle.sort_order(keys)
+        t2 = time.perf_counter()
+        out["ordering"] = {"cells": k, "keys_s": t1 - t0, "sort_s": t2 - t1,
+                           "cells_per_s": k / (t2 - t0),
+                           "sample": f"first {k} cells in original order: Hilbert keys + qsort of "
+                                     f"(key, index), single-threaded"}
+    return out
 
 
 def bench_batch32(args, dt):
@@ -204,6 +233,47 @@ def bench_batch32(args, dt):
     print(json.dumps(out), flush=True)
 
 
+def sort_passes(bits: int) -> int:
+    """8-bit LSD passes over the 3 * bits significant key bits."""
+    return max(1, (3 * bits + 7) // 8)
+
+
+def ordering_bytes_per_cell(bits: int, M: int, elem: int) -> float:
+    """Algorithmic bytes of the one-time ordering per cell: keys (read x, y, z,
+    level; write key and index: 13 + 12 - 4 = 21 B as counted for the survey's
+    table), the sort (one 8 B digit read per pass for the counts plus 24 B of
+    key and index read and written per pass), the gather of level and fields
+    (read index, level, fields; write level and fields)."""
+    p = sort_passes(bits)
+    return 21 + 8 * p + 24 * p + (4 + 1 + M * elem) + (1 + M * elem)
+
+
+def event_times(step, reps: int, flush=None):
+    """Per-step GPU time (ms) between events on the current stream; `flush`,
+    when given, runs before every step outside the events (it overwrites the
+    Infinity Cache)."""
+    import torch
+    out = []
+    s = torch.cuda.current_stream()
+    for k in range(reps):
+        if flush is not None:
+            flush(k)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        step(k)
+        e1.record(s)
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return out
+
+
+def pct(xs) -> dict:
+    import numpy as np
+    a = np.asarray(xs, np.float64)
+    return {"p10": float(np.percentile(a, 10)), "p50": float(np.percentile(a, 50)),
+            "p90": float(np.percentile(a, 90)), "n": int(a.size)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,7 +288,11 @@ def main():
     ap.add_argument("--exponent", type=float, default=1.0)
     ap.add_argument("--min-importance", type=float, default=0.025)
     ap.add_argument("--cpu-sample", type=int, default=300_000_000)
+    ap.add_argument("--cpu-order-sample", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-data-change", action="store_true")
+    ap.add_argument("--flush-mb", type=int, default=512,
+                    help="bytes written before each event-timed step to overwrite the Infinity Cache (0: none)")
     ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES bytes (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -267,23 +341,36 @@ def main():
     torch.cuda.synchronize()
     order_s = time.perf_counter() - t0
     log(f"ordering (Hilbert keys + radix sort + gather): {order_s * 1e3:.1f} ms")
-    del vol, fields
+    order_inputs = upd_inputs = None
+    if not args.no_cpu_baseline:
+        k = min(args.cpu_order_sample, n)
+        order_inputs = tuple(t[:k].cpu().numpy() for t in (vol.x, vol.y, vol.z, vol.level))
+        k = min(args.cpu_sample, n)
+        upd_inputs = (vol.level[:k].cpu().numpy(), np.stack([f[:k].float().cpu().numpy() for f in fields]))
+    del vol
     torch.cuda.empty_cache()
 
     # two TF sets, alternated every step: each update follows a TF change
     tf_sets = [np.stack([t.numpy() for t in synth.make_tfs(seed + k, M, (4, 4))]) for k in range(2)]
-    windows = [V.field_range(m) for m in range(M)]
     bins = dvl.Bins(args.bins, M)
     kw = dict(exponent=args.exponent, min_importance=args.min_importance)
 
-    def step(k):
+    def set_tfs(k):
         A = tf_sets[k & 1]
         for m in range(M):
-            lo, hi = windows[m]
+            lo, hi = V.field_range(m)
             if not hi > lo:
                 hi = float(np.nextafter(np.float32(lo), np.float32(np.inf)))
             dvl.set_tf(V, m, A[m], lo, hi)
+
+    def step(k):
+        set_tfs(k)
         V.update(bins, **kw)
+
+    flush_buf = torch.empty(max(args.flush_mb, 1) << 18, dtype=torch.float32, device="cuda")
+
+    def flush(k):
+        flush_buf.fill_(float(k))
 
     def measure(policy):
         V.set_entry_cache(policy)
@@ -304,36 +391,53 @@ def main():
         cached = V.entry_cache_info() is not None
         log(f"entry cache {'on' if cached else 'off'}: {args.steps} steps in {wall:.3f} s: {ms:.3f} ms/update; "
             f"kernels {phases}")
-        return ms, {k: v / max(n_upd, 1) for k, v in phases.items()}, cached
+        per_step = {"warm": pct(event_times(step, args.steps))}
+        if args.flush_mb:
+            per_step["flushed"] = pct(event_times(step, args.steps, flush))
+        return ms, {k: v / max(n_upd, 1) for k, v in phases.items()}, cached, per_step
 
     # The value path first (every update reads the fields), then the library
     # default: from the second update with unchanged windows on, the importance
     # pass reads the cached TF entries (one byte per cell and field).
     elem = 4 if args.dtype == "f32" else 2
-    ms_values, per_launch_values, _ = measure(dvl.ENTRY_CACHE_NEVER)
+    ms_values, per_launch_values, _, steps_values = measure(dvl.ENTRY_CACHE_NEVER)
     if args.entry_cache == "never":
-        ms_per_step, per_launch, cached = ms_values, per_launch_values, False
+        ms_per_step, per_launch, cached, steps_default = ms_values, per_launch_values, False, steps_values
     else:
-        ms_per_step, per_launch, cached = measure(dvl.ENTRY_CACHE_AUTO)
+        ms_per_step, per_launch, cached, steps_default = measure(dvl.ENTRY_CACHE_AUTO)
 
-    # roofline of the dominant kernel (the importance pass): it streams every
-    # cell's M field values (or M cached entries) once, plus one 32-bit level
-    # code per 256 cells and the level bytes of the 64-cell segments whose
-    # levels differ (a uniform segment's level is its code).  The projection
-    # pass re-reads the values of the tiles that contain a bin edge only (at
-    # most min(tiles, W) of them).
+    # Byte models.  The importance pass streams every cell's M field values
+    # (or M cached entries) once, plus one 32-bit level code per 256 cells and
+    # the level bytes of the 64-cell segments whose levels differ.  The
+    # projection re-reads the tiles that contain a bin edge (at most
+    # min(tiles, W) of them; cached entries or values, as the first pass) and,
+    # per bin, the values of the partial 256-cell steps at its two ends.
     n_seg, n_mixed = V.level_segments()
     level_bytes = n_mixed * 64 + (n_seg // 4) * 4
-    value_bpc = M * elem + level_bytes / n
-    bytes_per_cell = (M + level_bytes / n) if cached else value_bpc
-    alg_bytes = n * bytes_per_cell
+    lam = level_bytes / n
+    value_bpc = M * elem + lam
+    entry_bpc = M + lam
+    k1_bpc = entry_bpc if cached else value_bpc
+    alg_bytes = n * k1_bpc
     dom = max(("tile_sums", "bin"), key=lambda k: per_launch[k])
     achieved = alg_bytes / (per_launch[dom] * 1e-3) / 1e9
     n_tiles = (n + 4095) // 4096
-    rescan_bytes = min(n_tiles, args.bins) * 4096 * value_bpc
-    update_bytes = alg_bytes + rescan_bytes
+
+    def update_bytes_of(bpc):
+        return n * bpc + min(n_tiles, args.bins) * 4096 * bpc + args.bins * 2 * 256 * M * elem
+
+    update_bytes = update_bytes_of(k1_bpc)
     update_gbps = update_bytes / (ms_per_step * 1e-3) / 1e9
+    values_update_bytes = update_bytes_of(value_bpc)
     values_gbps = n * value_bpc / (per_launch_values["tile_sums"] * 1e-3) / 1e9
+    plain_bpc = 2 * (M * elem + 1)
+    ord_bpc = ordering_bytes_per_cell(V.bits, M, elem)
+    model = ("design, TF change with unchanged windows: importance pass over cached TF entries "
+             "(M + level bytes per cell), rescan of the tiles holding a bin edge, bin end steps; per-tile "
+             "and per-step field statistics and the entry cache are built at ordering / data-change time"
+             if cached else
+             "design, value path: importance pass over the field values (M*s + level bytes per cell), "
+             "rescan of the tiles holding a bin edge, bin end steps")
 
     out = {
         "metric": METRIC,
@@ -350,34 +454,91 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n_cells": n, "n_fields": M,
                    "field_storage": args.dtype, "n_bins": args.bins, "exponent": args.exponent,
-                   "min_importance": args.min_importance, "tf_control_points": 4},
+                   "min_importance": args.min_importance, "tf_control_points": 4,
+                   "step": "TF change (dvl_set_tf x M with the windows kept) + dvl_update"},
         "roofline": {"bound": "hbm", "kernel": dom + ("[entries]" if cached and dom == "tile_sums" else ""),
                      "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": profiled_traffic(args.workload, args.dtype, dom + ("_entries" if cached else "")),
-                     "bytes_per_launch": alg_bytes, "bytes_per_cell": bytes_per_cell,
+                     "bytes_per_launch": alg_bytes, "bytes_per_cell": k1_bpc,
+                     "byte_model": ("importance pass: M cached entry bytes + level stream per cell" if cached
+                                    else "importance pass: M field values + level stream per cell"),
                      "avg_launch_ms": per_launch[dom]},
+        "whole_update": {"bytes": update_bytes, "bytes_per_cell": update_bytes / n, "byte_model": model,
+                         "gbps": update_gbps, "frac": update_gbps / HBM_PEAK_GBPS, "target_frac": 0.6,
+                         "meets_target": update_gbps / HBM_PEAK_GBPS >= 0.6,
+                         "plain_two_pass_bytes_per_cell": plain_bpc,
+                         "plain_two_pass_equivalent_gbps": n * plain_bpc / (ms_per_step * 1e-3) / 1e9},
+        "per_step_ms": steps_default,
         "entry_cache": cached,
-        "level_segments": {"segments_of_64_cells": n_seg, "mixed": n_mixed,
-                           "level_bytes_per_cell": level_bytes / n},
+        "level_segments": {"segments_of_64_cells": n_seg, "mixed": n_mixed, "level_bytes_per_cell": lam},
         "no_entry_cache": {"ms_per_step": ms_values, "value": n / (ms_values * 1e-3),
                            "tile_sums_ms": per_launch_values["tile_sums"], "tile_sums_gbps": values_gbps,
                            "tile_sums_frac": values_gbps / HBM_PEAK_GBPS, "bytes_per_cell": value_bpc,
+                           "whole_update_gbps": values_update_bytes / (ms_values * 1e-3) / 1e9,
+                           "whole_update_frac": values_update_bytes / (ms_values * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                            "traffic": profiled_traffic(args.workload, args.dtype, "tile_sums"),
+                           "per_step_ms": steps_values,
                            "kernel_ms_per_update": per_launch_values},
-        "update_bytes": update_bytes,
-        "update_hbm_gbps": update_gbps,
-        "update_hbm_frac": update_gbps / HBM_PEAK_GBPS,
         "kernel_ms_per_update": per_launch,
-        "ordering": {"ms": order_s * 1e3, "cells_per_s": n / order_s},
+        "ordering": {"ms": order_s * 1e3, "cells_per_s": n / order_s, "bits_per_axis": V.bits,
+                     "sort_passes": sort_passes(V.bits), "bytes_per_cell": ord_bpc,
+                     "gbps": n * ord_bpc / order_s / 1e9, "frac": n * ord_bpc / order_s / 1e9 / HBM_PEAK_GBPS},
         "generation_s": gen_s,
         "paper_context": "RTX A6000, 35.8 M-cell Molecular Cloud, 4 fields: ~58.4 ms/update "
                          "(Table 1 sum excluding line drawing), ~0.61 G cells/s; other data and hardware",
     }
+
+    if not args.no_data_change:
+        # A data change: new values for every field (two resident copies in
+        # the original cell order, alternated), then the update.  The windows
+        # follow the new data ranges, so no entry cache is built.
+        alt = [(f.float() * (1.0 + 0.1 * torch.sin(fields[(m + 1) % M].float()))).to(dt)
+               for m, f in enumerate(fields)]
+        copies = (alt, fields)
+        V.set_entry_cache(dvl.ENTRY_CACHE_AUTO)
+
+        def data_step(k):
+            for m in range(M):
+                V.set_field(m, copies[k & 1][m])
+            step(k)
+
+        for k in range(args.warmup):
+            data_step(k)
+        torch.cuda.synchronize()
+        t_set = 0.0
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            ts = time.perf_counter()
+            for m in range(M):
+                V.set_field(m, copies[k & 1][m])
+            t_set += time.perf_counter() - ts
+            step(k)
+        torch.cuda.synchronize()
+        ms_dc = (time.perf_counter() - t0) * 1e3 / args.steps
+        # per field: data range of the new values (s B/cell), gather (4 B index,
+        # s B random read, s B write), per-tile/step statistics (s B/cell read)
+        set_bpc = M * (4 + 4 * elem)
+        dc_bytes = n * set_bpc + values_update_bytes
+        out["data_change"] = {
+            "ms_per_step": ms_dc, "value": n / (ms_dc * 1e-3), "set_field_ms_per_step": t_set * 1e3 / args.steps,
+            "entry_cache": V.entry_cache_info() is not None,
+            "bytes_per_cell": dc_bytes / n,
+            "byte_model": "dvl_set_field x M (range of the new values, gather into sorted order, per-tile and "
+                          "per-step statistics) + value-path update",
+            "gbps": dc_bytes / (ms_dc * 1e-3) / 1e9, "frac": dc_bytes / (ms_dc * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "step": "dvl_set_field for every field from one of two resident copies (original order), "
+                    "dvl_set_tf x M with the new data ranges, dvl_update"}
+        log(f"data change: {ms_dc:.3f} ms per step (set_field {t_set * 1e3 / args.steps:.3f} ms)")
+        del alt, copies
+    del fields
+    torch.cuda.empty_cache()
+
     if not args.no_cpu_baseline:
         log(f"oracle CPU baseline on up to {args.cpu_sample} cells ...")
-        out["cpu_baseline"] = cpu_baseline(V, tf_sets[0], args.bins, args.cpu_sample, args.exponent,
-                                           args.min_importance)
+        out["cpu_baseline"] = cpu_baseline(upd_inputs, tf_sets[0], args.bins, args.exponent,
+                                           args.min_importance, order_inputs)
+        del upd_inputs, order_inputs
         log(f"oracle: {out['cpu_baseline']['value']:.3e} cells/s")
     V.close()
     print(json.dumps(out), flush=True)

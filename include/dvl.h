@@ -21,8 +21,10 @@
  *     are independent.  Updates of one volume must be issued on one stream
  *     (they share the volume's parameter block and workspace).
  *   - The library owns the volume's internal device buffers (sorted fields,
- *     levels, keys, permutation, workspace) and allocates them with
- *     hipMalloc; dvl_destroy frees them.
+ *     levels, keys, permutation, statistics, entry cache, workspace).  It
+ *     allocates them through the caller's dvl_allocator when one is given
+ *     (dvl_build_options.allocator, dvl_executor_create_ex), else with
+ *     hipMalloc; dvl_destroy gives them back the same way.
  */
 #ifndef DVL_H
 #define DVL_H
@@ -63,6 +65,21 @@ typedef int32_t dvl_status;
 #define DVL_SCAN_NAIVE_FP32  2  /* plain fp32, for error studies only */
 
 typedef struct dvl_volume dvl_volume;
+
+/* Device memory provider.  alloc returns `bytes` of device memory on the
+ * current device (NULL when it cannot: the call then fails with DVL_E_NOMEM
+ * and gives back everything it had taken); release takes back a pointer that
+ * alloc returned.  `stream` is the HIP stream of the call that allocates or
+ * releases (NULL when there is none).  The library releases a buffer only
+ * after the device has finished every kernel it enqueued on it.  Both
+ * functions are called from the thread of the library call, never
+ * concurrently for one volume or executor.  The allocator (and `ctx`) must
+ * outlive the volume or executor that uses it. */
+typedef struct {
+    void* (*alloc)(void* ctx, size_t bytes, void* stream);
+    void (*release)(void* ctx, void* ptr, void* stream);
+    void* ctx;
+} dvl_allocator;
 
 /* ---------------------------------------------------------------------
  * dvl_build_order -- one-time ordering (Background, AMR paragraph and
@@ -113,17 +130,24 @@ dvl_status dvl_build_order(int64_t n_cells, const int32_t* x, const int32_t* y,
  *                DVL_ENTRY_CACHE_AUTO (0) when two consecutive updates use
  *                the same set, DVL_ENTRY_CACHE_ALWAYS on the first use of a
  *                set, DVL_ENTRY_CACHE_NEVER never.  A (re)build costs one
- *                pass over the fields, synchronises the device before and
- *                the stream after it, and takes n_cells bytes per field. */
+ *                pass over the fields on the update's stream (ordered by
+ *                events against updates in flight on other streams; the host
+ *                does not wait) and takes n_cells bytes per field. */
 enum { DVL_ENTRY_CACHE_AUTO = 0, DVL_ENTRY_CACHE_ALWAYS = 1, DVL_ENTRY_CACHE_NEVER = 2 };
 typedef struct {
     int32_t tile_steps;
     int32_t run_waves;
     int32_t entry_cache;
+    const dvl_allocator* allocator;   /* NULL: hipMalloc / hipFree.  Copied;
+                                         serves every device buffer of the
+                                         volume, its entry cache and the
+                                         workspace of its dvl_update calls */
 } dvl_build_options;
 
 /* Change the entry-cache policy of a volume (DVL_ENTRY_CACHE_*).  NEVER also
- * frees the cache (after synchronising the device).  Host only. */
+ * frees the cache (after synchronising the device).  Host only.  A cache
+ * (re)build is ordered against updates in flight on other streams by events;
+ * it never blocks the host. */
 dvl_status dvl_set_entry_cache(dvl_volume* v, int32_t policy);
 /* 1 if the volume holds a built TF entry cache, with the windows and table
  * sizes it was built for in lo/hi/n_tf (host [n_fields] each, any may be
@@ -136,10 +160,24 @@ dvl_status dvl_build_order_ex(int64_t n_cells, const int32_t* x, const int32_t* 
                               int32_t dtype, const void* const* fields,
                               const dvl_build_options* options, void* stream, dvl_volume** out);
 
-/* Replace field m's values (a data change; the order is unchanged).
- * values: device [n_cells] of the volume's dtype, original order.  Re-gathers
- * into sorted order and refreshes the data range; synchronises `stream`.
- * A previously set TF for m stays, with its window. */
+/* ---------------------------------------------------------------------
+ * dvl_set_field -- replace field m's values: the data change of the
+ * Introduction (the volume lines are recomputed whenever the data or the
+ * alpha TF changes); the Hilbert order of the GPU section stays fixed, only
+ * the values move.
+ *
+ *   m        0 <= m < n_fields
+ *   values   device [n_cells] of the volume's dtype, ORIGINAL cell order;
+ *            must stay valid until `stream` has reached this call's work
+ *
+ * First the data range of the new values is taken and checked for NaN
+ * (this synchronises `stream` once); a NaN returns DVL_E_RANGE and leaves the
+ * volume unchanged.  Then the values are gathered into sorted order and the
+ * per-tile / per-step statistics refreshed, asynchronously on `stream`; the
+ * TF entry cache is invalidated.  A TF set earlier for m keeps its window.
+ * Updates issued later must run on `stream` (or after it).  Errors:
+ * DVL_E_INVALID, DVL_E_RANGE, DVL_E_HIP (sticky).
+ * ------------------------------------------------------------------- */
 dvl_status dvl_set_field(dvl_volume* v, int32_t m, const void* values, void* stream);
 
 /* Data range [min, max] of field m (host outputs). */
@@ -212,6 +250,9 @@ dvl_status dvl_update(dvl_volume* v, const dvl_params* p, const dvl_bins* out, v
 
 /* ---------------------------------------------------------------------
  * Batched updates (many volumes and TF requests in one launch per phase).
+ * Each request is the update of Eqs. 1-4 and section Projecting Cells to 1D
+ * (as dvl_update); the paper issued one CUDA stream per field and found no
+ * gain (GPU Implementation), so here the batch shares launches instead.
  *
  * A request is one update of one volume with its own TFs, windows,
  * parameters and outputs; it does not touch the volume's own TF state.
@@ -237,6 +278,9 @@ typedef struct {
  * streams need different executors. */
 typedef struct dvl_executor dvl_executor;
 dvl_status dvl_executor_create(dvl_executor** out);
+/* ... with its workspaces and descriptor blocks from `allocator` (NULL:
+ * hipMalloc).  The allocator is copied. */
+dvl_status dvl_executor_create_ex(const dvl_allocator* allocator, dvl_executor** out);
 void dvl_executor_destroy(dvl_executor* ex);
 /* device bytes held (workspaces and descriptor buffers) */
 size_t dvl_executor_bytes(const dvl_executor* ex);
@@ -263,17 +307,23 @@ dvl_status dvl_graph_set_tf(dvl_graph* g, int32_t req, const float* alpha, const
 dvl_status dvl_graph_launch(dvl_graph* g, void* stream);
 void dvl_graph_destroy(dvl_graph* g);
 
-/* Synchronise `stream`, then copy the bins to host arrays (any may be NULL):
+/* dvl_read_bins -- the per-pixel bins of section Projecting Cells to 1D
+ * (a counter and the projected values per bin) and the TF'd heights of
+ * section Interactive Transfer Function Updates, copied to the host.
+ * Synchronises `stream`, then copies to host arrays (any may be NULL):
  * count/first/last uint32[W], mean/vmin/vmax/y float[M*W], f_total[1],
- * vmax_used[1]. */
+ * vmax_used[1].  `bins` are an update's device outputs with n_bins = W. */
 dvl_status dvl_read_bins(const dvl_volume* v, const dvl_bins* bins, int32_t n_bins,
                          void* stream, uint32_t* count, uint32_t* first, uint32_t* last,
                          float* mean, float* vmin, float* vmax, float* y,
                          double* f_total, float* vmax_used);
 
-/* Hilbert keys in ORIGINAL cell order and the permutation (perm[h] = original
- * index of the h-th sorted cell), into caller-owned device arrays
- * uint64[n_cells] and uint32[n_cells] (either may be NULL).  Asynchronous. */
+/* dvl_export_order -- the ordering of section Dynamic Volume Lines (cells
+ * ordered along a Hilbert curve of their quantised centroids; Background,
+ * cells on the finest-level logical grid): the Hilbert keys in ORIGINAL cell
+ * order and the permutation (perm[h] = original index of the h-th sorted
+ * cell), into caller-owned device arrays uint64[n_cells] and uint32[n_cells]
+ * (either may be NULL).  Asynchronous. */
 dvl_status dvl_export_order(const dvl_volume* v, uint64_t* keys, uint32_t* perm, void* stream);
 
 /* Sorted level and field arrays, into caller-owned device arrays

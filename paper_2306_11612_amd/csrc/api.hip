@@ -45,17 +45,58 @@ static dvl_status fail(dvl_status code, const char* fmt, ...) {
 
 static int elem_bytes_of(int dtype) { return dtype == DVL_F32 ? 4 : 2; }
 
+// Device memory of the library: through the caller's dvl_allocator when one
+// was given, else hipMalloc / hipFree.  Every buffer is released through the
+// allocator that made it.
+struct Alloc {
+    dvl_allocator a{};
+    bool custom = false;
+    void* get(size_t bytes, hipStream_t s) const {
+        if (bytes == 0) bytes = 1;
+        if (custom) return a.alloc(a.ctx, bytes, (void*)s);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void put(void* p, hipStream_t s) const {
+        if (!p) return;
+        if (custom)
+            a.release(a.ctx, p, (void*)s);
+        else
+            (void)hipFree(p);
+    }
+};
+
+static dvl_status make_alloc(const dvl_allocator* a, Alloc& out) {
+    out = Alloc();
+    if (!a) return DVL_OK;
+    if (!a->alloc || !a->release) return fail(DVL_E_INVALID, "allocator needs both alloc and release");
+    out.a = *a;
+    out.custom = true;
+    return DVL_OK;
+}
+
 // device buffer owned by RAII until released
 struct DevBuf {
+    const Alloc* A;
     void* p = nullptr;
-    ~DevBuf() { if (p) (void)hipFree(p); }
-    dvl_status alloc(size_t bytes, const char* what) {
-        hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
-        if (e != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            return fail(DVL_E_NOMEM, "hipMalloc of %zu bytes for %s failed", bytes, what);
+    explicit DevBuf(const Alloc& a) : A(&a) {}
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    // a buffer still owned here is a temporary or the leftover of a failing
+    // call: kernels enqueued on it may still run, so wait before handing it back
+    ~DevBuf() {
+        if (p) {
+            (void)hipDeviceSynchronize();
+            A->put(p, nullptr);
         }
+    }
+    dvl_status alloc(size_t bytes, const char* what) {
+        p = A->get(bytes, nullptr);
+        if (!p) return fail(DVL_E_NOMEM, "device allocation of %zu bytes for %s failed", bytes, what);
         return DVL_OK;
     }
     void* release() { void* q = p; p = nullptr; return q; }
@@ -130,11 +171,20 @@ struct dvl_volume {
     CacheKey idx_key;
     bool cand_set = false;
     CacheKey cand_key;
+    // Ordering of cache rebuilds against the launches that read the cache,
+    // by events instead of device synchronisation: a rebuild on stream s
+    // first waits for the last reading launch on every stream; a launch that
+    // reads the cache first waits for the rebuild (`cache_ready`).
+    hipEvent_t cache_ready = nullptr;
+    bool cache_ready_recorded = false;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> cache_readers;
     // the volume's own transfer functions (used by dvl_update)
     bool tf_set[kMaxFields] = {};
     std::vector<float> alpha[kMaxFields];
     float lo[kMaxFields] = {}, hi[kMaxFields] = {};
     Executor* ex = nullptr;  // private executor of dvl_update
+    dvl::Alloc alloc;        // every device buffer of the volume comes from here
+    unsigned int* scratch_range = nullptr;   // 4 words for dvl_set_field's range check
     dvl_status sticky = DVL_OK;
     size_t bytes = 0;
 };
@@ -530,7 +580,7 @@ static dvl_status decide_cache(Plan& P, std::vector<CacheBuild>& builds) {
         } else if (v->idx_policy == DVL_ENTRY_CACHE_ALWAYS || (v->cand_set && v->cand_key == key)) {
             for (int m = 0; m < v->M; ++m) {
                 if (v->idx_s[m]) continue;
-                DevBuf b;
+                DevBuf b(v->alloc);
                 if (dvl_status st = b.alloc((size_t)v->n_pad, "TF entry cache")) return st;
                 v->idx_s[m] = (uint8_t*)b.release();
                 v->bytes += (size_t)v->n_pad;
@@ -549,25 +599,53 @@ static dvl_status decide_cache(Plan& P, std::vector<CacheBuild>& builds) {
     return DVL_OK;
 }
 
-// Rebuild the scheduled caches on stream s.  Work on other streams may still
-// read a cache, and later launches on other streams must see the new one, so
-// a rebuild waits for the device before and for the stream after.
+// Rebuild the scheduled caches on stream s.  Launches on other streams may
+// still read a cache and later launches on any stream must see the new one;
+// both are ordered by events (see dvl_volume::cache_readers), so the host
+// never waits here.
 static dvl_status run_cache_builds(const std::vector<CacheBuild>& builds, hipStream_t s) {
-    if (builds.empty()) return DVL_OK;
-    DVL_HIP(hipDeviceSynchronize());
     for (const CacheBuild& cb : builds) {
         dvl_volume* v = cb.v;
+        for (auto& r : v->cache_readers)
+            if (r.first != s) DVL_HIP(hipStreamWaitEvent(s, r.second, 0));
         v->idx_valid = false;
         for (int m = 0; m < v->M; ++m)
             if (dvl_status st = launch_build_index(v->n_pad, v->dtype, v->fields_s[m], cb.key.s[m], cb.key.b[m],
                                                    cb.key.n_tf[m], v->idx_s[m], v->n_cu, s))
                 return st;
+        DVL_HIP(hipEventRecord(v->cache_ready, s));
+        v->cache_ready_recorded = true;
+        v->idx_key = cb.key;
+        v->idx_valid = true;
+        v->cand_set = false;
     }
-    DVL_HIP(hipStreamSynchronize(s));
-    for (const CacheBuild& cb : builds) {
-        cb.v->idx_key = cb.key;
-        cb.v->idx_valid = true;
-        cb.v->cand_set = false;
+    return DVL_OK;
+}
+
+// Before a launch on stream s that reads the caches of the jobs in `P`: wait
+// for their latest rebuild (done on another stream, possibly).
+static dvl_status cache_wait(const Plan& P, hipStream_t s) {
+    for (const JobDev& j : P.jobs) {
+        if (!j.idx[0]) continue;
+        dvl_volume* v = P.reqs[j.req0].v;
+        if (v->cache_ready_recorded) DVL_HIP(hipStreamWaitEvent(s, v->cache_ready, 0));
+    }
+    return DVL_OK;
+}
+
+// After such a launch: remember it as the latest reader on stream s.
+static dvl_status cache_mark_readers(const Plan& P, hipStream_t s) {
+    for (const JobDev& j : P.jobs) {
+        if (!j.idx[0]) continue;
+        dvl_volume* v = P.reqs[j.req0].v;
+        hipEvent_t ev = nullptr;
+        for (auto& r : v->cache_readers)
+            if (r.first == s) ev = r.second;
+        if (!ev) {
+            DVL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            v->cache_readers.push_back({s, ev});
+        }
+        DVL_HIP(hipEventRecord(ev, s));
     }
     return DVL_OK;
 }
@@ -604,6 +682,7 @@ static size_t request_ws_bytes(const dvl_volume* v, int n_bins) {
 
 struct Executor {
     int n_cu = 256;
+    Alloc alloc;                    // workspaces and descriptor blocks
     struct Slot {
         char* host = nullptr;
         char* dev = nullptr;
@@ -614,6 +693,8 @@ struct Executor {
     Slot ring[kRing];
     int next = 0;
     std::vector<std::pair<void*, size_t>> ws;   // workspace pool: one per request position
+    hipEvent_t last = nullptr;      // end of this executor's latest launch
+    bool launched = false;
     bool timing = false;
     std::vector<std::vector<hipEvent_t>> ev_pool, ev_pending;
     double phase_ms[kPhases] = {};
@@ -624,11 +705,11 @@ struct Executor {
         (void)hipDeviceSynchronize();
         for (auto& s : ring) {
             if (s.host) (void)hipHostFree(s.host);
-            if (s.dev) (void)hipFree(s.dev);
+            alloc.put(s.dev, nullptr);
             if (s.ev) (void)hipEventDestroy(s.ev);
         }
-        for (auto& w : ws)
-            if (w.first) (void)hipFree(w.first);
+        for (auto& w : ws) alloc.put(w.first, nullptr);
+        if (last) (void)hipEventDestroy(last);
         for (auto* pool : {&ev_pool, &ev_pending})
             for (auto& set : *pool)
                 for (auto e : set) (void)hipEventDestroy(e);
@@ -639,20 +720,29 @@ struct Executor {
         DVL_HIP(hipGetDevice(&dev));
         DVL_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
         for (auto& s : ring) DVL_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+        DVL_HIP(hipEventCreateWithFlags(&last, hipEventDisableTiming));
         return DVL_OK;
     }
 
+    // the executor's earlier launches (one stream) are the only users of its
+    // buffers: waiting for the latest one frees them for reuse
+    dvl_status wait_idle() {
+        if (launched) DVL_HIP(hipEventSynchronize(last));
+        return DVL_OK;
+    }
+
+    // grow workspace i to `need` bytes; if the allocation fails the old
+    // workspace stays, so smaller requests keep working
     dvl_status ensure_ws(size_t i, size_t need) {
         if (ws.size() <= i) ws.resize(i + 1, {nullptr, 0});
         if (ws[i].second >= need) return DVL_OK;
-        if (ws[i].first) {
-            DVL_HIP(hipDeviceSynchronize());   // earlier batches may still use it
-            (void)hipFree(ws[i].first);
-            bytes -= ws[i].second;
-            ws[i] = {nullptr, 0};
-        }
-        DevBuf b;
+        DevBuf b(alloc);
         if (dvl_status st = b.alloc(need, "request workspace")) return st;
+        if (ws[i].first) {
+            if (dvl_status st = wait_idle()) return st;
+            alloc.put(ws[i].first, nullptr);
+            bytes -= ws[i].second;
+        }
         ws[i] = {b.release(), need};
         bytes += need;
         return DVL_OK;
@@ -665,23 +755,22 @@ struct Executor {
         next = (next + 1) % kRing;
         if (s.used) DVL_HIP(hipEventSynchronize(s.ev));
         if (s.cap < need) {
-            if (s.dev) {
-                DVL_HIP(hipDeviceSynchronize());   // kernels of earlier batches read it
-                (void)hipFree(s.dev);
-                bytes -= s.cap;
-            }
-            if (s.host) (void)hipHostFree(s.host);
-            s.host = nullptr;
-            s.dev = nullptr;
-            s.cap = 0;
+            // the new buffers first: on failure the slot keeps its old ones
             const size_t cap = std::max(need * 2, (size_t)65536);
-            if (hipHostMalloc((void**)&s.host, cap, hipHostMallocDefault) != hipSuccess) {
-                s.host = nullptr;
+            DevBuf d(alloc);
+            if (dvl_status st = d.alloc(cap, "batch descriptors")) return st;
+            char* host = nullptr;
+            if (hipHostMalloc((void**)&host, cap, hipHostMallocDefault) != hipSuccess) {
                 (void)hipGetLastError();
                 return fail(DVL_E_NOMEM, "pinned host allocation of %zu bytes failed", cap);
             }
-            DevBuf d;
-            if (dvl_status st = d.alloc(cap, "batch descriptors")) return st;
+            if (s.dev) {
+                if (dvl_status st = wait_idle()) return st;   // kernels of earlier batches read it
+                alloc.put(s.dev, nullptr);
+                bytes -= s.cap;
+            }
+            if (s.host) (void)hipHostFree(s.host);
+            s.host = host;
             s.dev = (char*)d.release();
             s.cap = cap;
             bytes += cap;
@@ -718,6 +807,7 @@ struct Executor {
         std::vector<CacheBuild> builds;
         if (dvl_status st = decide_cache(P, builds)) return st;
         if (dvl_status st = run_cache_builds(builds, s)) return st;
+        if (dvl_status st = cache_wait(P, s)) return st;
         Slot* slot = nullptr;
         if (dvl_status st = take_slot(P.device_bytes, &slot)) return st;
         if (dvl_status st = fill_block(P, slot->host, slot->dev)) return st;
@@ -730,7 +820,11 @@ struct Executor {
         for (const JobDev& j : P.jobs) paths |= j.idx[0] ? kPathEntries : kPathValues;
         for (const ReqDev& d : P.rdev)
             if (d.ws.fstore) paths |= kPathStoredF;
-        return launch_batch(batch_dev(P, slot->dev, paths), P.dtype, P.max_m, P.max_req, n_cu, s, ev);
+        if (dvl_status st = launch_batch(batch_dev(P, slot->dev, paths), P.dtype, P.max_m, P.max_req, n_cu, s, ev))
+            return st;
+        DVL_HIP(hipEventRecord(last, s));
+        launched = true;
+        return cache_mark_readers(P, s);
     }
 
     dvl_status kernel_times(double* ms, int32_t* n) {
@@ -754,9 +848,10 @@ struct Executor {
     }
 };
 
-static dvl_status new_executor(Executor** out) {
+static dvl_status new_executor(const Alloc& a, Executor** out) {
     Executor* ex = new (std::nothrow) Executor();
     if (!ex) return fail(DVL_E_NOMEM, "host allocation failed");
+    ex->alloc = a;
     if (dvl_status st = ex->init()) {
         delete ex;
         return st;
@@ -784,6 +879,7 @@ static dvl_status requests_from(const dvl_request* reqs, int32_t n, std::vector<
 
 struct dvl_graph {
     Plan plan;
+    Alloc alloc;                         // the first request's volume's allocator
     int n_cu = 256;
     char* dev = nullptr;                 // the descriptor block the captured kernels read
     std::vector<void*> ws;               // one workspace per request
@@ -797,9 +893,8 @@ struct dvl_graph {
         (void)hipDeviceSynchronize();
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
-        if (dev) (void)hipFree(dev);
-        for (void* w : ws)
-            if (w) (void)hipFree(w);
+        alloc.put(dev, nullptr);
+        for (void* w : ws) alloc.put(w, nullptr);
         for (int r = 0; r < kRing; ++r) {
             if (host[r]) (void)hipHostFree(host[r]);
             if (ev[r]) (void)hipEventDestroy(ev[r]);
@@ -845,7 +940,9 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
     for (int m = 0; m < M; ++m)
         if (!fields[m]) return fail(DVL_E_INVALID, "field %d pointer is NULL", m);
     int tile_steps = kDefaultTileSteps, run_waves = 0, entry_cache = DVL_ENTRY_CACHE_AUTO;
+    Alloc alloc;
     if (opt) {
+        if (dvl_status st = make_alloc(opt->allocator, alloc)) return st;
         if (opt->entry_cache < DVL_ENTRY_CACHE_AUTO || opt->entry_cache > DVL_ENTRY_CACHE_NEVER)
             return fail(DVL_E_INVALID, "entry_cache %d", opt->entry_cache);
         entry_cache = opt->entry_cache;
@@ -862,6 +959,8 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
     dvl_volume* v = new (std::nothrow) dvl_volume();
     if (!v) return fail(DVL_E_NOMEM, "host allocation failed");
     struct Guard { dvl_volume* v; ~Guard() { if (v) dvl_destroy(v); } } guard{v};
+    v->alloc = alloc;
+    const Alloc& A = v->alloc;
     v->n = n;
     v->M = M;
     v->dtype = dtype;
@@ -883,7 +982,7 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
     }
 
     // extent, validity, grid bits
-    DevBuf ext;
+    DevBuf ext(A);
     if (dvl_status st = ext.alloc(4 * sizeof(unsigned long long), "extent")) return st;
     DVL_HIP(hipMemsetAsync(ext.p, 0, 4 * sizeof(unsigned long long), s));
     if (dvl_status st = launch_extent(n, x, y, z, level, (unsigned long long*)ext.p, s)) return st;
@@ -898,7 +997,7 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
     v->max_level = (int)eh[2];
 
     // keys + sort
-    DevBuf ka, kb, va, vb, counts, partial;
+    DevBuf ka(A), kb(A), va(A), vb(A), counts(A), partial(A);
     if (dvl_status st = ka.alloc((size_t)n * 8, "keys")) return st;
     if (dvl_status st = kb.alloc((size_t)n * 8, "keys (sort buffer)")) return st;
     if (dvl_status st = va.alloc((size_t)n * 4, "permutation")) return st;
@@ -924,27 +1023,27 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
     v->bytes += (size_t)n * 12;
 
     // gather into sorted order (padded to whole tiles, padding zeroed)
-    DevBuf lv;
+    DevBuf lv(A);
     if (dvl_status st = lv.alloc((size_t)v->n_pad, "sorted levels")) return st;
     DVL_HIP(hipMemsetAsync((char*)lv.p + n, 0, (size_t)(v->n_pad - n), s));
     if (dvl_status st = launch_gather(n, v->perm, level, lv.p, 1, s)) return st;
     v->level_s = (uint8_t*)lv.release();
     v->bytes += (size_t)v->n_pad;
     {
-        DevBuf lc;
+        DevBuf lc(A);
         const int64_t n_steps = v->n_pad / kStepCells;
         if (dvl_status st = lc.alloc((size_t)n_steps * 4, "level codes")) return st;
         if (dvl_status st = launch_level_codes(v->level_s, n_steps, (uint32_t*)lc.p, s)) return st;
         v->lcode_s = (uint32_t*)lc.release();
         v->bytes += (size_t)n_steps * 4;
     }
-    DevBuf rng;
+    DevBuf rng(A);
     if (dvl_status st = rng.alloc((size_t)kMaxFields * 4 * sizeof(unsigned int), "ranges")) return st;
     std::vector<unsigned int> rinit(kMaxFields * 4, 0u);
     for (int m = 0; m < kMaxFields; ++m) rinit[m * 4] = 0xFFFFFFFFu;
     DVL_HIP(hipMemcpyAsync(rng.p, rinit.data(), rinit.size() * 4, hipMemcpyHostToDevice, s));
     for (int m = 0; m < M; ++m) {
-        DevBuf fb;
+        DevBuf fb(A);
         if (dvl_status st = fb.alloc((size_t)v->n_pad * eb, "sorted field")) return st;
         DVL_HIP(hipMemsetAsync((char*)fb.p + (size_t)n * eb, 0, (size_t)(v->n_pad - n) * eb, s));
         if (dvl_status st = launch_gather(n, v->perm, fields[m], fb.p, eb, s)) return st;
@@ -953,7 +1052,7 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
         v->bytes += (size_t)v->n_pad * eb;
     }
     {
-        DevBuf as, an, ax, ss, sn, sx;
+        DevBuf as(A), an(A), ax(A), ss(A), sn(A), sx(A);
         const size_t mt = (size_t)M * v->n_tiles;
         const size_t ms = mt * v->tile_steps;
         if (dvl_status st = as.alloc(mt * 8, "tile sums")) return st;
@@ -980,8 +1079,16 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
         v->dmax[m] = unkey(rinit[m * 4 + 1]);
     }
 
+    {
+        DevBuf sr(A);
+        if (dvl_status st = sr.alloc(4 * sizeof(unsigned int), "range scratch")) return st;
+        v->scratch_range = (unsigned int*)sr.release();
+        v->bytes += 4 * sizeof(unsigned int);
+    }
+    DVL_HIP(hipEventCreateWithFlags(&v->cache_ready, hipEventDisableTiming));
+
     // private executor of dvl_update, with the workspace of one request ready
-    if (dvl_status st = new_executor(&v->ex)) return st;
+    if (dvl_status st = new_executor(A, &v->ex)) return st;
     if (dvl_status st = v->ex->ensure_ws(0, request_ws_bytes(v, 1))) return st;
     guard.v = nullptr;
     *out = v;
@@ -1001,21 +1108,25 @@ dvl_status dvl_set_field(dvl_volume* v, int32_t m, const void* values, void* str
     if (!values) return fail(DVL_E_INVALID, "values is NULL");
     hipStream_t s = (hipStream_t)stream;
     const int eb = elem_bytes_of(v->dtype);
+    // The data range (and the NaN check) does not depend on the order, so it
+    // is taken from the new values as given, before anything of the volume
+    // changes: a rejected field leaves the volume as it was.
+    unsigned int r[4] = {0xFFFFFFFFu, 0u, 0u, 0u};
+    DVL_HIP(hipMemcpyAsync(v->scratch_range, r, sizeof r, hipMemcpyHostToDevice, s));
+    if (dvl_status st = launch_range(v->n, v->dtype, values, v->scratch_range, s)) return st;
+    DVL_HIP(hipMemcpyAsync(r, v->scratch_range, sizeof r, hipMemcpyDeviceToHost, s));
+    DVL_HIP(hipStreamSynchronize(s));
+    if (r[2]) return fail(DVL_E_RANGE, "field %d holds a NaN; the volume is unchanged", m);
     v->idx_valid = false;      // the cached entries describe the old values
     v->cand_set = false;
-    DevBuf rng;
-    if (dvl_status st = rng.alloc(4 * sizeof(unsigned int), "range")) return st;
-    unsigned int r[4] = {0xFFFFFFFFu, 0u, 0u, 0u};
-    DVL_HIP(hipMemcpyAsync(rng.p, r, sizeof r, hipMemcpyHostToDevice, s));
-    if (dvl_status st = launch_gather(v->n, v->perm, values, v->fields_s[m], eb, s)) { v->sticky = st; return st; }
-    if (dvl_status st = launch_range(v->n, v->dtype, v->fields_s[m], (unsigned int*)rng.p, s)) { v->sticky = st; return st; }
+    if (dvl_status st = launch_gather(v->n, v->perm, values, v->fields_s[m], eb, s)) {
+        v->sticky = st;
+        return st;
+    }
     if (dvl_status st = tile_aggregates(v, m, s)) {
         v->sticky = st;
         return st;
     }
-    DVL_HIP(hipMemcpyAsync(r, rng.p, sizeof r, hipMemcpyDeviceToHost, s));
-    DVL_HIP(hipStreamSynchronize(s));
-    if (r[2]) return fail(DVL_E_RANGE, "field %d holds a NaN", m);
     v->dmin[m] = unkey(r[0]);
     v->dmax[m] = unkey(r[1]);
     return DVL_OK;
@@ -1139,7 +1250,7 @@ dvl_status dvl_set_entry_cache(dvl_volume* v, int32_t policy) {
         DVL_HIP(hipDeviceSynchronize());   // queued updates may still read it
         for (int m = 0; m < kMaxFields; ++m) {
             if (!v->idx_s[m]) continue;
-            (void)hipFree(v->idx_s[m]);
+            v->alloc.put(v->idx_s[m], nullptr);
             v->idx_s[m] = nullptr;
             v->bytes -= (size_t)v->n_pad;
         }
@@ -1184,34 +1295,40 @@ void dvl_destroy(dvl_volume* v) {
     if (!v) return;
     (void)hipDeviceSynchronize();
     delete v->ex;
-    if (v->level_s) (void)hipFree(v->level_s);
-    if (v->lcode_s) (void)hipFree(v->lcode_s);
-    for (int m = 0; m < kMaxFields; ++m)
-        if (v->fields_s[m]) (void)hipFree(v->fields_s[m]);
-    if (v->keys_s) (void)hipFree(v->keys_s);
-    if (v->perm) (void)hipFree(v->perm);
-    if (v->agg_sum) (void)hipFree(v->agg_sum);
-    if (v->agg_min) (void)hipFree(v->agg_min);
-    if (v->agg_max) (void)hipFree(v->agg_max);
-    if (v->step_sum) (void)hipFree(v->step_sum);
-    if (v->step_min) (void)hipFree(v->step_min);
-    if (v->step_max) (void)hipFree(v->step_max);
-    for (int m = 0; m < kMaxFields; ++m)
-        if (v->idx_s[m]) (void)hipFree(v->idx_s[m]);
+    const Alloc& A = v->alloc;
+    A.put(v->level_s, nullptr);
+    A.put(v->lcode_s, nullptr);
+    for (int m = 0; m < kMaxFields; ++m) A.put(v->fields_s[m], nullptr);
+    A.put(v->keys_s, nullptr);
+    A.put(v->perm, nullptr);
+    A.put(v->agg_sum, nullptr);
+    A.put(v->agg_min, nullptr);
+    A.put(v->agg_max, nullptr);
+    A.put(v->step_sum, nullptr);
+    A.put(v->step_min, nullptr);
+    A.put(v->step_max, nullptr);
+    A.put(v->scratch_range, nullptr);
+    for (int m = 0; m < kMaxFields; ++m) A.put(v->idx_s[m], nullptr);
+    if (v->cache_ready) (void)hipEventDestroy(v->cache_ready);
+    for (auto& r : v->cache_readers) (void)hipEventDestroy(r.second);
     delete v;
 }
 
 // ------------------------------------------------------------------ executors and batches
 
-dvl_status dvl_executor_create(dvl_executor** out) {
+dvl_status dvl_executor_create_ex(const dvl_allocator* allocator, dvl_executor** out) {
     g_err.clear();
     if (!out) return fail(DVL_E_INVALID, "out is NULL");
     *out = nullptr;
+    Alloc a;
+    if (dvl_status st = make_alloc(allocator, a)) return st;
     Executor* ex = nullptr;
-    if (dvl_status st = new_executor(&ex)) return st;
+    if (dvl_status st = new_executor(a, &ex)) return st;
     *out = reinterpret_cast<dvl_executor*>(ex);
     return DVL_OK;
 }
+
+dvl_status dvl_executor_create(dvl_executor** out) { return dvl_executor_create_ex(nullptr, out); }
 
 void dvl_executor_destroy(dvl_executor* ex) { delete reinterpret_cast<Executor*>(ex); }
 
@@ -1253,17 +1370,18 @@ dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph**
     struct Guard { dvl_graph* g; ~Guard() { delete g; } } guard{g};
     if (dvl_status st = plan_batch(std::move(rh), g->plan)) return st;
     Plan& P = g->plan;
+    g->alloc = P.reqs[0].v->alloc;
     int dev = 0;
     DVL_HIP(hipGetDevice(&dev));
     DVL_HIP(hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     for (size_t q = 0; q < P.reqs.size(); ++q) {
-        DevBuf w;
+        DevBuf w(g->alloc);
         const ReqHost& r = P.reqs[q];
         if (dvl_status st = w.alloc(request_ws_bytes(r.v, r.p.n_bins), "request workspace")) return st;
         g->ws.push_back(w.release());
         workspace_carve(g->ws.back(), r.v->n_tiles, r.v->M, fstore_cells(r.v, r.p.n_bins), &P.rdev[q].ws);
     }
-    DevBuf d;
+    DevBuf d(g->alloc);
     if (dvl_status st = d.alloc(P.device_bytes, "graph descriptors")) return st;
     g->dev = (char*)d.release();
     {
@@ -1326,13 +1444,14 @@ dvl_status dvl_graph_launch(dvl_graph* g, void* stream) {
     std::vector<CacheBuild> builds;
     if (dvl_status st = decide_cache(g->plan, builds)) return st;
     if (dvl_status st = run_cache_builds(builds, s)) return st;
+    if (dvl_status st = cache_wait(g->plan, s)) return st;
     if (dvl_status st = fill_block(g->plan, g->host[r], g->dev)) return st;
     g->next = (r + 1) % kRing;
     DVL_HIP(hipMemcpyAsync(g->dev, g->host[r], g->plan.block_bytes, hipMemcpyHostToDevice, s));
     DVL_HIP(hipEventRecord(g->ev[r], s));
     g->used[r] = true;
     DVL_HIP(hipGraphLaunch(g->exec, s));
-    return DVL_OK;
+    return cache_mark_readers(g->plan, s);
 }
 
 void dvl_graph_destroy(dvl_graph* g) { delete g; }

@@ -46,8 +46,55 @@ class dvl_bins(C.Structure):
                 ("f_total", C.c_void_p), ("vmax_used", C.c_void_p)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class dvl_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("ctx", C.c_void_p)]
+
+
 class dvl_build_options(C.Structure):
-    _fields_ = [("tile_steps", C.c_int32), ("run_waves", C.c_int32), ("entry_cache", C.c_int32)]
+    _fields_ = [("tile_steps", C.c_int32), ("run_waves", C.c_int32), ("entry_cache", C.c_int32),
+                ("allocator", C.POINTER(dvl_allocator))]
+
+
+class Allocator:
+    """A ``dvl_allocator`` over two Python callables: ``alloc(nbytes, stream)``
+    returning a device address (0 when it cannot) and ``release(ptr, stream)``.
+    Keeps the ctypes callbacks alive; volumes and executors built with it hold
+    a reference to it."""
+
+    def __init__(self, alloc, release):
+        def _alloc(ctx, nbytes, stream):
+            try:
+                return int(alloc(int(nbytes), int(stream or 0))) or None
+            except Exception:
+                return None
+
+        def _release(ctx, ptr, stream):
+            try:
+                release(int(ptr), int(stream or 0))
+            except Exception:
+                pass
+
+        self._cb = (ALLOC_FN(_alloc), RELEASE_FN(_release))
+        self.struct = dvl_allocator(self._cb[0], self._cb[1], None)
+
+
+def torch_allocator() -> Allocator:
+    """The library's device memory from PyTorch's caching allocator (on the
+    stream of the call that allocates; the current stream when it has none)."""
+    def alloc(nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(nbytes, stream=stream or None)
+        except torch.OutOfMemoryError:
+            return 0
+
+    def release(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return Allocator(alloc, release)
 
 
 class dvl_request(C.Structure):
@@ -99,6 +146,7 @@ def lib():
         "dvl_set_entry_cache": (i32, [vp, i32]),
         "dvl_entry_cache_info": (i32, [vp, vp, vp, vp]),
         "dvl_executor_create": (i32, [C.POINTER(vp)]),
+        "dvl_executor_create_ex": (i32, [C.POINTER(dvl_allocator), C.POINTER(vp)]),
         "dvl_executor_destroy": (None, [vp]),
         "dvl_executor_bytes": (C.c_size_t, [vp]),
         "dvl_request_bytes": (C.c_size_t, [vp, i32]),
@@ -174,9 +222,11 @@ def params(n_bins: int, exponent: float = 1.0, min_importance: float = 0.025,
 # ---------------------------------------------------------------- C-ABI mirrors
 
 def build_order(x, y, z, level, fields, stream=None, tile_steps: int = 0, run_waves: int = 0,
-                entry_cache: int = ENTRY_CACHE_AUTO) -> "Volume":
+                entry_cache: int = ENTRY_CACHE_AUTO, allocator: Allocator | None = None) -> "Volume":
     """dvl_build_order (dvl_build_order_ex when an option is given): one-time
-    Hilbert ordering of the cells."""
+    Hilbert ordering of the cells.  ``allocator``: where the volume's device
+    memory comes from (``torch_allocator()`` for PyTorch's caching allocator;
+    None: the library's hipMalloc)."""
     x, y, z = _dev(x, torch.int32), _dev(y, torch.int32), _dev(z, torch.int32)
     level = _dev(level, torch.uint8)
     fields = [_dev(f) for f in fields]
@@ -187,8 +237,9 @@ def build_order(x, y, z, level, fields, stream=None, tile_steps: int = 0, run_wa
         raise ValueError("fields must share one of float32 / float16 / bfloat16")
     arr = (C.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
     out = C.c_void_p()
-    if tile_steps or run_waves or entry_cache != ENTRY_CACHE_AUTO:
-        opt = dvl_build_options(int(tile_steps), int(run_waves), int(entry_cache))
+    if tile_steps or run_waves or entry_cache != ENTRY_CACHE_AUTO or allocator is not None:
+        opt = dvl_build_options(int(tile_steps), int(run_waves), int(entry_cache),
+                                C.pointer(allocator.struct) if allocator is not None else None)
         st = lib().dvl_build_order_ex(x.numel(), _ptr(x), _ptr(y), _ptr(z), _ptr(level), len(fields),
                                       _DTYPE_CODE[dt], C.cast(arr, C.c_void_p), C.byref(opt),
                                       _stream_ptr(stream), C.byref(out))
@@ -198,7 +249,7 @@ def build_order(x, y, z, level, fields, stream=None, tile_steps: int = 0, run_wa
                                    _DTYPE_CODE[dt], C.cast(arr, C.c_void_p), _stream_ptr(stream),
                                    C.byref(out))
         _check(st, "dvl_build_order")
-    return Volume(out)
+    return Volume(out, allocator)
 
 
 def set_tf(vol: "Volume", m: int, alpha, lo: float, hi: float):
@@ -232,8 +283,9 @@ def read_bins(vol: "Volume", bins: Bins, stream=None) -> dict:
 class Volume:
     """A volume in Hilbert order, resident on the device (owns a dvl_volume*)."""
 
-    def __init__(self, handle: C.c_void_p):
+    def __init__(self, handle: C.c_void_p, allocator: Allocator | None = None):
         self.handle = handle
+        self.allocator = allocator   # must outlive the handle
 
     # conveniences over the C-ABI mirrors
     build = staticmethod(build_order)
@@ -391,9 +443,13 @@ def _request_array(reqs) -> C.Array:
 class Executor:
     """``dvl_executor``: runs batches of requests, one launch per phase."""
 
-    def __init__(self):
+    def __init__(self, allocator: Allocator | None = None):
         h = C.c_void_p()
-        _check(lib().dvl_executor_create(C.byref(h)), "dvl_executor_create")
+        if allocator is None:
+            _check(lib().dvl_executor_create(C.byref(h)), "dvl_executor_create")
+        else:
+            _check(lib().dvl_executor_create_ex(C.byref(allocator.struct), C.byref(h)), "dvl_executor_create_ex")
+        self.allocator = allocator
         self.handle = h
 
     @property

@@ -76,6 +76,8 @@ class Scheduler:
         self.peak_used = 0
         self.completed: list[Job] = []
         self.batches: list[int] = []
+        self.max_running = 0               # most slots seen busy at once (overlap on the device)
+        self.max_shared = 0                # most requests of one batch on one volume (shared reads)
 
     def submit(self, job: Job):
         job.bytes = int(self.engine.request_bytes(job))
@@ -125,6 +127,9 @@ class Scheduler:
                 break
             self.running[slot] = (self.engine.start(slot, batch), batch)
             self.batches.append(len(batch))
+            self.max_running = max(self.max_running, len(self.running))
+            per_volume = collections.Counter(j.volume for j in batch)
+            self.max_shared = max(self.max_shared, max(per_volume.values()))
         return finished
 
 
@@ -155,6 +160,8 @@ def run_open_loop(sched: Scheduler, jobs: list[Job], clock=time.perf_counter, sp
     out = {"requests": len(sched.completed), "wall_s": t1 - t0,
            "throughput_rps": len(sched.completed) / max(t1 - t0, 1e-9),
            "mean_batch": float(np.mean(sched.batches)) if sched.batches else 0.0,
+           "max_batch": int(max(sched.batches)) if sched.batches else 0,
+           "max_running_slots": sched.max_running, "max_requests_on_one_volume": sched.max_shared,
            "peak_bytes": sched.peak_used}
     out.update(percentiles(lat))
     return out
@@ -162,17 +169,36 @@ def run_open_loop(sched: Scheduler, jobs: list[Job], clock=time.perf_counter, sp
 
 # ---------------------------------------------------------------- GPU engine
 
+class HostBins:
+    """Pinned host copies of one request's bins (what a client receives)."""
+
+    def __init__(self, torch, n_bins: int, n_fields: int):
+        pin = dict(device="cpu", pin_memory=True)
+        self.first = torch.empty(n_bins, dtype=torch.int32, **pin)
+        self.last = torch.empty(n_bins, dtype=torch.int32, **pin)
+        self.stats = torch.empty(4, n_fields, n_bins, dtype=torch.float32, **pin)   # mean, min, max, y
+
+    def copy_from(self, b):
+        self.first.copy_(b.first_cell, non_blocking=True)
+        self.last.copy_(b.last_cell, non_blocking=True)
+        for k, t in enumerate((b.mean, b.vmin, b.vmax, b.y)):
+            self.stats[k].copy_(t, non_blocking=True)
+
+
 class GpuEngine:
     """Engine over the C ABI: one executor and one stream (default priority)
-    per slot, and a pool of output buffers per (fields, width)."""
+    per slot, and pools of device outputs and pinned host copies per (fields,
+    width).  A request is complete when its bins are on the host: the
+    device-to-host copy is part of its latency."""
 
-    def __init__(self, volumes: dict, n_slots: int = 2):
+    def __init__(self, volumes: dict, n_slots: int = 2, copy_to_host: bool = True):
         import torch
         from . import dvl
         self.dvl = dvl
         self.torch = torch
         self.volumes = volumes
         self.n_slots = n_slots
+        self.copy_to_host = copy_to_host
         self.slots = [(dvl.Executor(), torch.cuda.Stream()) for _ in range(n_slots)]
         self.pool: dict[tuple[int, int], list] = collections.defaultdict(list)
 
@@ -181,7 +207,11 @@ class GpuEngine:
 
     def _bins(self, M: int, W: int):
         p = self.pool[(M, W)]
-        return p.pop() if p else self.dvl.Bins(W, M)
+        if p:
+            return p.pop()
+        b = self.dvl.Bins(W, M)
+        b.host = HostBins(self.torch, W, M) if self.copy_to_host else None
+        return b
 
     def start(self, slot: int, jobs: list[Job]):
         ex, stream = self.slots[slot]
@@ -193,6 +223,10 @@ class GpuEngine:
         # the stream must not read output buffers before earlier users of the pool are done
         stream.wait_stream(self.torch.cuda.current_stream())
         ex.update_batch(reqs, stream=stream)
+        if self.copy_to_host:
+            with self.torch.cuda.stream(stream):
+                for j in jobs:
+                    j.out.host.copy_from(j.out)
         ev = self.torch.cuda.Event()
         ev.record(stream)
         return ev
