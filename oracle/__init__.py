@@ -69,6 +69,11 @@ def bind(path: str):
                              C.c_void_p, C.c_void_p]
     L.ora_field_range.restype = None
     L.ora_field_range.argtypes = [C.c_int64, C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+    L.ora_bin_histograms.restype = C.c_int32
+    L.ora_bin_histograms.argtypes = [C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                     C.c_float, C.c_float, C.c_void_p]
+    L.ora_rasterize.restype = C.c_int32
+    L.ora_rasterize.argtypes = [C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
     return L
 
 
@@ -221,3 +226,28 @@ def default_windows(fields):
         fields = fields[None, :]
     r = [field_range(f) for f in fields]
     return (np.array([a for a, _ in r], np.float32), np.array([b for _, b in r], np.float32))
+
+
+RASTER_POLYLINE, RASTER_BARS = 0, 1
+
+
+def bin_histograms(values, first, last, n_buckets: int, lo: float, hi: float) -> np.ndarray:
+    """Per-bin histograms [W, H] of sorted `values` over the bins' cell ranges."""
+    values = _c(values, np.float32)
+    first, last = _c(first, np.uint32), _c(last, np.uint32)
+    W = first.size
+    out = np.empty((W, int(n_buckets)), np.uint32)
+    rc = lib().ora_bin_histograms(values.size, _p(values), W, _p(first), _p(last), int(n_buckets),
+                                  float(lo), float(hi), _p(out))
+    if rc != 0:
+        raise ValueError("oracle histograms rejected their arguments")
+    return out
+
+
+def rasterize(y, n_rows: int, mode: int = RASTER_POLYLINE) -> np.ndarray:
+    """Image [H, W] (uint8 0/1, row 0 at the bottom) of one line of heights."""
+    y = _c(y, np.float32)
+    img = np.empty((int(n_rows), y.size), np.uint8)
+    if lib().ora_rasterize(y.size, _p(y), int(n_rows), int(mode), _p(img)) != 0:
+        raise ValueError("oracle raster rejected its arguments")
+    return img

@@ -347,3 +347,63 @@ int32_t ora_update(int64_t n, int32_t n_fields, const uint8_t* level, const floa
     if (!cell_e) free(E);
     return 0;
 }
+
+
+/* ------------------------------------------------------------------ */
+/* Per-bin histograms (histogram heatmap)                              */
+/* ------------------------------------------------------------------ */
+
+/* Prototypical User Interface section: besides the lines, volume-line plots
+ * can show a histogram heatmap, i.e. per bin the distribution of the values
+ * of its cells.  The buckets partition the window [lo, hi] as the entries of
+ * a table of H entries do, so a value's bucket is its entry under that
+ * quantiser. */
+int32_t ora_bin_histograms(int64_t n, const float* values, int32_t n_bins, const uint32_t* first,
+                           const uint32_t* last, int32_t n_buckets, float lo, float hi, uint32_t* counts)
+{
+    if (n < 1 || n_bins < 1 || n_buckets < 1 || !(lo < hi)) return -1;
+    float s, b;
+    ora_quantiser(n_buckets, lo, hi, &s, &b);
+    for (int64_t i = 0; i < (int64_t)n_bins * n_buckets; ++i) counts[i] = 0;
+    for (int32_t bin = 0; bin < n_bins; ++bin) {
+        if (first[bin] > last[bin] || (int64_t)last[bin] >= n) continue;
+        for (int64_t h = first[bin]; h <= (int64_t)last[bin]; ++h) {
+            int32_t k = ora_tf_index(values[h], s, b, n_buckets);
+            counts[(int64_t)bin * n_buckets + k] += 1;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Line rasterisation (RasterizeLines)                                 */
+/* ------------------------------------------------------------------ */
+
+static int32_t ora_row(float y, int32_t n_rows)
+{
+    float t = y * (float)n_rows;
+    if (!(t >= 0.0f)) return 0;
+    int32_t r = (int32_t)floorf(t);
+    return r > n_rows - 1 ? n_rows - 1 : r;
+}
+
+/* GPU Implementation section: the volume lines are drawn either as
+ * polylines through the bin heights or as bar charts. */
+int32_t ora_rasterize(int32_t n_bins, const float* y, int32_t n_rows, int32_t mode, uint8_t* img)
+{
+    if (n_bins < 1 || n_rows < 1 || (mode != ORA_RASTER_POLYLINE && mode != ORA_RASTER_BARS)) return -1;
+    memset(img, 0, (size_t)n_bins * (size_t)n_rows);
+    for (int32_t b = 0; b < n_bins; ++b) {
+        int32_t r0 = ora_row(y[b], n_rows), lo, hi;
+        if (mode == ORA_RASTER_BARS) {
+            lo = 0;
+            hi = r0;
+        } else {
+            int32_t r1 = b + 1 < n_bins ? ora_row(y[b + 1], n_rows) : r0;
+            lo = r0 < r1 ? r0 : r1;
+            hi = r0 < r1 ? r1 : r0;
+        }
+        for (int32_t r = lo; r <= hi; ++r) img[(int64_t)r * n_bins + b] = 1;
+    }
+    return 0;
+}

@@ -106,6 +106,28 @@ int32_t ora_update(int64_t n, int32_t n_fields, const uint8_t* level, const floa
 /* Data range of one field (min and max over all n values). */
 void ora_field_range(int64_t n, const float* v, float* vmin, float* vmax);
 
+/* ---- histogram heatmap of a volume line (section Prototypical User
+ *      Interface: the histogram heatmap of Weissenboeck et al.'s volume
+ *      lines) ---- */
+/* For every bin b of an update (sorted cells first[b]..last[b]) the number
+ * of its cells whose value falls in bucket k of [lo, hi]: counts[b*H + k],
+ * with the bucket of a value chosen as a TF entry is (ora_tf_index with the
+ * quantiser of [lo, hi] for H entries; values outside the window go to the
+ * end buckets).  values[n] in sorted order.  Returns 0, or -1 on invalid
+ * arguments. */
+int32_t ora_bin_histograms(int64_t n, const float* values, int32_t n_bins, const uint32_t* first,
+                           const uint32_t* last, int32_t n_buckets, float lo, float hi, uint32_t* counts);
+
+/* ---- RasterizeLines (GPU Implementation section: the volume lines drawn as
+ *      polylines or as bar charts into the plot) ---- */
+enum { ORA_RASTER_POLYLINE = 0, ORA_RASTER_BARS = 1 };
+/* Image of one line of W heights y[b] in [0, 1] on H rows (row 0 at the
+ * bottom): row(y) = min(H - 1, max(0, floor(y * H))) with y * H in fp32.
+ * Polyline: column b holds row(y[b]) and every row between it and
+ * row(y[b + 1]).  Bars: column b holds rows 0 .. row(y[b]).  img[r*W + b]
+ * is 1 for a drawn pixel, else 0.  Returns 0, or -1 on invalid arguments. */
+int32_t ora_rasterize(int32_t n_bins, const float* y, int32_t n_rows, int32_t mode, uint8_t* img);
+
 #ifdef __cplusplus
 }
 #endif

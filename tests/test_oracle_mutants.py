@@ -14,6 +14,7 @@ import pytest
 import oracle
 import test_oracle_hilbert as H
 import test_oracle_update as U
+import test_oracle_views as V
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "dvl_oracle.c")
 
@@ -45,6 +46,13 @@ MUTANTS = [
     ("height_from_max_not_mean", "ora_tf_index((float)out->mean[o], s[m], b[m], n_tf);",
      "ora_tf_index(out->vmax[o], s[m], b[m], n_tf);"),
     ("degenerate_not_handled", "for (int64_t h = 0; h < n; ++h) f[h] = 1.0;", ";"),
+    ("histogram_last_cell_dropped", "for (int64_t h = first[bin]; h <= (int64_t)last[bin]; ++h) {",
+     "for (int64_t h = first[bin]; h < (int64_t)last[bin]; ++h) {"),
+    ("histogram_window_reversed", "ora_quantiser(n_buckets, lo, hi, &s, &b);", "ora_quantiser(n_buckets, hi, lo, &s, &b);"),
+    ("raster_round_not_floor", "int32_t r = (int32_t)floorf(t);", "int32_t r = (int32_t)floorf(t + 0.5f);"),
+    ("raster_next_height_ignored", "int32_t r1 = b + 1 < n_bins ? ora_row(y[b + 1], n_rows) : r0;",
+     "int32_t r1 = r0;"),
+    ("raster_bars_from_one", "            lo = 0;\n            hi = r0;", "            lo = 1;\n            hi = r0;"),
 ]
 
 
@@ -71,6 +79,13 @@ def _pins():
         lambda: U.test_vmax_range_literal(oracle),
         lambda: U.test_vmax_range_is_not_an_upper_bound(oracle),
         lambda: U.test_structural_invariants(oracle, 12, 257, 2.0, 0.025),
+        lambda: V.test_histogram_hand_example(oracle),
+        lambda: V.test_histogram_counts_sum_to_bin_sizes_with_straddles(oracle),
+        lambda: V.test_histogram_matches_numpy_away_from_bucket_edges(oracle),
+        lambda: V.test_histogram_values_outside_the_window_go_to_the_end_buckets(oracle),
+        lambda: V.test_raster_constant_line_is_one_row(oracle),
+        lambda: V.test_raster_hand_example(oracle),
+        lambda: V.test_raster_invariants(oracle, 0),
     ]
     for s in range(24):
         cases.append(lambda s=s: U.test_against_exact_rational_bruteforce(oracle, s))
