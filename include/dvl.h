@@ -336,7 +336,8 @@ dvl_status dvl_export_sorted(const dvl_volume* v, uint8_t* level, void* const* f
  * Per-kernel timing of updates (profiling aid).  While enabled, every
  * dvl_update records HIP events on its stream around each of its kernels:
  * phase 0 exact max(V) (VMAX_EXACT only), 1 tile sums of the importance,
- * 2 carry scan, 3 projection + bin reduction, 4 edge-bin merge.
+ * 2 carry scan, 3 projection (tile classification and rescan: bin cell
+ * ranges), 4 bin statistics (mean, min, max, height per bin).
  * dvl_kernel_times synchronises on the recorded events, returns the summed
  * milliseconds per phase (ms[5]) over the updates since the last call and
  * their number, and resets the sums.  Enabling adds a few microseconds per

@@ -820,7 +820,7 @@ struct Executor {
         for (const JobDev& j : P.jobs) paths |= j.idx[0] ? kPathEntries : kPathValues;
         for (const ReqDev& d : P.rdev)
             if (d.ws.fstore) paths |= kPathStoredF;
-        if (dvl_status st = launch_batch(batch_dev(P, slot->dev, paths), P.dtype, P.max_m, P.max_req, n_cu, s, ev))
+        if (dvl_status st = launch_batch(batch_dev(P, slot->dev, paths), P.dtype, P.max_m, P.max_req, n_cu, s, kDescriptorLayout, ev))
             return st;
         DVL_HIP(hipEventRecord(last, s));
         launched = true;
@@ -1405,7 +1405,7 @@ dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph**
         return hip_fail(e, "hipStreamBeginCapture");
     }
     const dvl_status cst = launch_batch(batch_dev(P, g->dev, kPathValues | kPathEntries | kPathStoredF), P.dtype, P.max_m,
-                                        P.max_req, g->n_cu, cs, nullptr);
+                                        P.max_req, g->n_cu, cs, kDescriptorLayout, nullptr);
     const hipError_t ee = hipStreamEndCapture(cs, &g->graph);
     (void)hipStreamDestroy(cs);
     if (cst != DVL_OK) return cst;

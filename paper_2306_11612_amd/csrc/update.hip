@@ -10,27 +10,30 @@
 //   K2 k_carry        per request: exclusive scan of the run totals (Eq. 4
 //                     across runs; fp64 or compensated fp32), made monotone
 //   K3a k_classify    per (request, tile), one lane each: if the tile's pixel
-//                     interval lies inside one bin, its precomputed field
-//                     statistics are its record; otherwise the tile is queued
+//                     interval lies inside one bin, the whole tile is that
+//                     bin's part; otherwise the tile is queued
 //   K3b k_bin         per queued tile: recompute f, monotone in-tile prefix,
-//                     pixel interval of every cell; bins complete inside the
-//                     tile are finalised directly, its first and last bin go
-//                     to per-tile partial records
-//   K4 k_edges        per (request, bin): merge the partial records of bins
-//                     shared by tiles in tile order; mean, min, max, height
+//                     pixel interval of every cell; the cell range of every
+//                     bin that starts and ends inside the tile, and of the
+//                     tile's first and last bin (per-tile records)
+//   K4 k_bin_stats    per (request, bin): the bin's cell range (merged from
+//                     the records of the tiles it touches), then its mean,
+//                     min and max per field from the values of its partial
+//                     end steps and the per-step and per-tile statistics of
+//                     the steps and tiles it covers whole; the height
 //
 // The paper's GPU version runs the projection once per field with global
 // atomics on the W bins (its Table 1 bottleneck).  Here the projection is
 // hierarchical over tiles (the paper's future-work suggestion): only tiles
-// that contain a bin edge are read again, all fields at once and atomic-free
-// (per-lane accumulators while a 256-cell step stays in one bin, a per-bin
-// wave reduction at bin edges).  Results are bitwise deterministic and do not
-// depend on what else is in the batch.
+// that contain a bin edge are read again, to find where bins start and end;
+// no atomics on bins, and the statistics of a bin cost work in proportion to
+// its two ends, not to its cells.  Results are bitwise deterministic and do
+// not depend on what else is in the batch.
 //
-// K0, K1 and K3b depend on the field storage type; they live in
-// update_kernels.hpp and are instantiated once per type in update_f32.hip,
-// update_f16.hip and update_bf16.hip.  This file holds K2, K3a, K4, the
-// per-tile statistics and the TF entry cache builder.
+// K0, K1, K3b and K4 depend on the field storage type and the field count;
+// they live in update_kernels.hpp and are instantiated once per (type,
+// count) in translation units the build generates.  This file holds K2, K3a,
+// the per-tile statistics, the TF entry cache builder and the launcher.
 #include "update_kernels.hpp"
 
 namespace dvl {
@@ -46,8 +49,6 @@ size_t workspace_bytes(int64_t T, int M, int64_t fcells) {
     b += al256((size_t)(T + 1) * 8);       // run_base
     b += 2 * al256((size_t)T * 4);         // head/tail bin
     b += 2 * al256((size_t)2 * T * 4);     // rec first/last
-    b += al256((size_t)2 * M * T * 8);     // rec_sum
-    b += 2 * al256((size_t)2 * M * T * 4); // rec min/max
     b += al256(8 * 8);                     // scalars
     b += al256((size_t)fcells * 4);        // stored importance
     return b;
@@ -63,9 +64,6 @@ void workspace_carve(void* base, int64_t T, int M, int64_t fcells, UpdWorkspace*
     w->tail_bin = (int32_t*)take((size_t)T * 4);
     w->rec_first = (uint32_t*)take((size_t)2 * T * 4);
     w->rec_last = (uint32_t*)take((size_t)2 * T * 4);
-    w->rec_sum = (double*)take((size_t)2 * M * T * 8);
-    w->rec_min = (float*)take((size_t)2 * M * T * 4);
-    w->rec_max = (float*)take((size_t)2 * M * T * 4);
     w->scal = (double*)take(8 * 8);
     w->fstore = fcells ? (float*)take((size_t)fcells * 4) : nullptr;
 }
@@ -218,9 +216,9 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(BatchDev b) {
 }
 
 // K3a.  A tile whose pixel interval lies inside one bin puts every cell in
-// that bin: its record is the tile's precomputed statistics and no cell is
-// read (the projection is hierarchical over tiles).  Other tiles are queued
-// for K3b, one wave-aggregated atomic per wave.
+// that bin: its head record is the whole tile and no cell is read (the
+// projection is hierarchical over tiles).  Other tiles are queued for K3b,
+// one wave-aggregated atomic per wave.
 __global__ __launch_bounds__(256) void k_classify(BatchDev bd) {
     const int64_t u = (int64_t)block_x() * 256 + thread_x();
     bool need = false;
@@ -230,17 +228,10 @@ __global__ __launch_bounds__(256) void k_classify(BatchDev bd) {
         const JobDev& j = bd.jobs[q.job];
         path = q.ws.fstore ? 2 : (j.idx[0] ? 1 : 0);
         const int64_t t = u - q.k3_unit0;
-        const int64_t T = j.n_tiles;
         const TileSpan sp = tile_span(q, j, t);
         if (sp.b0 == sp.b1) {
             const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
             const int64_t tbase = t * tile_cells;
-            for (int m = 0; m < j.M; ++m) {
-                const int64_t o = (int64_t)m * T + t;    // head record of field m
-                gstore<double>(q.ws.rec_sum, o, gload<double>(j.agg_sum, o));
-                gstore<float>(q.ws.rec_min, o, gload<float>(j.agg_min, o));
-                gstore<float>(q.ws.rec_max, o, gload<float>(j.agg_max, o));
-            }
             gstore<uint32_t>(q.ws.rec_first, t, (uint32_t)tbase);
             gstore<uint32_t>(q.ws.rec_last, t, (uint32_t)(min(tbase + tile_cells, j.n) - 1));
             gstore<int32_t>(q.ws.head_bin, t, sp.b0);
@@ -263,110 +254,6 @@ __global__ __launch_bounds__(256) void k_classify(BatchDev bd) {
                 gstore<uint64_t>(bd.rescan_queue, p * bd.k3_units + base + (uint32_t)__popcll(mask & lanemask_lt()),
                                  (uint64_t)u);
         }
-    }
-}
-
-// ------------------------------------------------------------------ K4
-
-// First index in [0, T) where `pred` turns false (pred true on a prefix, false
-// after), found by the whole wave: each round the 64 lanes probe 64 evenly
-// spaced points of the remaining range, so three or four rounds of loads
-// replace the ~17 dependent loads of a binary search over 10^5 tiles.
-template <typename Pred>
-__device__ __forceinline__ int64_t wave_partition_point(int64_t T, Pred pred) {
-    const int lane = lane_id();
-    int64_t lo = 0, hi = T;          // the answer lies in [lo, hi]
-    while (lo < hi) {
-        const int64_t step = (hi - lo + kWave - 1) / kWave;
-        const int64_t p = lo + step * lane;
-        const bool t = p < hi && pred(p);
-        const int c = __popcll(__ballot(t));          // lanes 0 .. c-1 hold true
-        if (c == 0) return lo;                       // pred(lo) is false
-        const int64_t new_lo = lo + step * (c - 1) + 1;
-        hi = min(hi, lo + step * c);
-        lo = new_lo;
-    }
-    return lo;
-}
-
-template <int MT>
-__global__ __launch_bounds__(256) void k_edges(BatchDev bd) {
-    const int lane = lane_id();
-    const int64_t u = (int64_t)block_x() * (256 / kWave) + thread_x() / kWave;
-    if (u >= bd.k4_units) return;
-    const int qi = find_req_k4(bd, u);
-    const ReqDev& q = bd.reqs[qi];
-    const JobDev& j = bd.jobs[q.job];
-    const int M = fields_of<MT>(j.M);
-    const int b = (int)(u - q.k4_unit0);
-    if (b == 0 && lane == 0) {
-        gstore<double>(q.f_total, 0, gload<double>(q.ws.scal, 0));
-        gstore<float>(q.vmax_used, 0, gload<float>(q.vmax_dev, 0));
-    }
-    const int64_t T = j.n_tiles;
-    const int32_t* hb = q.ws.head_bin;
-    const int32_t* tb = q.ws.tail_bin;
-    // tiles touching bin b: t0 = first with tail >= b, t1 = last with head <= b
-    const int64_t t0 = wave_partition_point(T, [&](int64_t t) { return gload<int32_t>(tb, t) < b; });
-    const int64_t t1 = wave_partition_point(T, [&](int64_t t) { return gload<int32_t>(hb, t) <= b; }) - 1;
-    if (t0 <= t1 && t0 == t1 && hb[t0] < b && b < tb[t0]) return;  // finalised by the projection pass
-
-    Seg<MT> acc;
-    seg_clear(acc);
-    for (int64_t t = t0 + lane; t <= t1; t += kWave) {
-        const int r = gload<int32_t>(hb, t) == b ? 0 : (gload<int32_t>(tb, t) == b ? 1 : -1);
-        if (r < 0) continue;
-        Seg<MT> s;
-        s.first = gload<uint32_t>(q.ws.rec_first, r * T + t);
-        s.last = gload<uint32_t>(q.ws.rec_last, r * T + t);
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            if (m < M) {
-                const int64_t o = ((int64_t)r * M + m) * T + t;
-                s.sum[m] = gload<double>(q.ws.rec_sum, o);
-                s.mn[m] = gload<float>(q.ws.rec_min, o);
-                s.mx[m] = gload<float>(q.ws.rec_max, o);
-            } else {
-                s.sum[m] = 0.0;
-                s.mn[m] = INFINITY;
-                s.mx[m] = -INFINITY;
-            }
-        }
-        acc = seg_combine(acc, s);
-    }
-    // deterministic butterfly merge
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        acc.sum[m] = wave_sum_d(acc.sum[m]);
-        acc.mn[m] = wave_min_f(acc.mn[m]);
-        acc.mx[m] = wave_max_f(acc.mx[m]);
-    }
-    acc.first = wave_min_u32(acc.first);
-    acc.last = wave_max_u32(acc.last);
-    if (lane != 0) return;
-    if (acc.first == 0xFFFFFFFFu) {  // no cell (cannot happen with a positive total width)
-        gstore<uint32_t>(q.first_cell, b, 0xFFFFFFFFu);
-        gstore<uint32_t>(q.last_cell, b, 0xFFFFFFFEu);
-        for (int m = 0; m < M; ++m) {
-            const int64_t o = (int64_t)m * q.W + b;
-            gstore<float>(q.mean, o, 0.0f);
-            gstore<float>(q.vmin, o, INFINITY);
-            gstore<float>(q.vmax, o, -INFINITY);
-            gstore<float>(q.y, o, 0.0f);
-        }
-        return;
-    }
-    const uint32_t cnt = acc.last - acc.first + 1u;
-    gstore<uint32_t>(q.first_cell, b, acc.first);
-    gstore<uint32_t>(q.last_cell, b, acc.last);
-    for (int m = 0; m < M; ++m) {
-        const float mean = (float)(acc.sum[m] / (double)cnt);
-        const int e = tf_entry(mean, q.s[m], q.b[m], q.nmax[m]);
-        const int64_t o = (int64_t)m * q.W + b;
-        gstore<float>(q.mean, o, mean);
-        gstore<float>(q.vmin, o, acc.mn[m]);
-        gstore<float>(q.vmax, o, acc.mx[m]);
-        gstore<float>(q.y, o, gload<float>(q.tf, q.tf_off[m] + e));
     }
 }
 
@@ -531,24 +418,16 @@ dvl_status launch_classify(const BatchDev& b, hipStream_t s) {
     return DVL_OK;
 }
 
-dvl_status launch_edges(const BatchDev& b, int mt, hipStream_t s) {
-    const unsigned g = (unsigned)std::max<int64_t>(1, (b.k4_units + 3) / 4);
-    switch (mt) {
-        case 1: hipLaunchKernelGGL((k_edges<1>), dim3(g), dim3(256), 0, s, b); break;
-        case 2: hipLaunchKernelGGL((k_edges<2>), dim3(g), dim3(256), 0, s, b); break;
-        case 4: hipLaunchKernelGGL((k_edges<4>), dim3(g), dim3(256), 0, s, b); break;
-        case 8: hipLaunchKernelGGL((k_edges<8>), dim3(g), dim3(256), 0, s, b); break;
-        default: hipLaunchKernelGGL((k_edges<16>), dim3(g), dim3(256), 0, s, b); break;
-    }
-    DVL_HIP(hipGetLastError());
-    return DVL_OK;
-}
-
 dvl_status launch_batch(const BatchDev& b, int dtype, int max_m, int max_req, int n_cu, hipStream_t s,
-                        hipEvent_t* ev) {
-    if (dtype == DVL_F16) return launch_batch_f16(b, max_m, max_req, n_cu, s, ev);
-    if (dtype == DVL_BF16) return launch_batch_bf16(b, max_m, max_req, n_cu, s, ev);
-    return launch_batch_f32(b, max_m, max_req, n_cu, s, ev);
+                        uint64_t layout, hipEvent_t* ev) {
+    if (layout != kDescriptorLayout) {
+        set_error("descriptor layout mismatch between library objects (%llx vs %llx): rebuild the library",
+                  (unsigned long long)layout, (unsigned long long)kDescriptorLayout);
+        return DVL_E_INVALID;
+    }
+    if (dtype == DVL_F16) return launch_s<F16>(b, max_m, max_req, n_cu, s, layout, ev);
+    if (dtype == DVL_BF16) return launch_s<BF16>(b, max_m, max_req, n_cu, s, layout, ev);
+    return launch_s<F32>(b, max_m, max_req, n_cu, s, layout, ev);
 }
 
 }  // namespace dvl

@@ -15,7 +15,7 @@ constexpr int kCellsPerLane = 4;                 // one 4-vector per field per s
 constexpr int kStepCells = kWave * kCellsPerLane;    // 256 cells per wave step
 constexpr int kDefaultTileSteps = 16;            // 4096-cell tiles unless tuned
 constexpr int kMaxReqPerJob = 8;
-constexpr int kPhases = 5;                       // exact vmax, tile sums, carry, bin, edges
+constexpr int kPhases = 5;                       // exact vmax, tile sums, carry, bin edges, bin statistics
 constexpr int kPathValues = 1;                   // jobs that read the field values
 constexpr int kPathEntries = 2;                  // jobs that read cached TF entries
 constexpr int kPathStoredF = 4;                  // requests whose projection reads stored f
@@ -26,13 +26,10 @@ struct UpdWorkspace {
     double* local_prefix; // [T]  sum of the importance of earlier tiles of the same run
     double* run_total;    // [R]  sum over each run of consecutive tiles
     double* run_base;     // [R + 1]  exclusive prefix of run totals, run_base[R] = F_tot
-    int32_t* head_bin;    // [T]
-    int32_t* tail_bin;    // [T]
-    uint32_t* rec_first;  // [2][T]  head records then tail records
+    int32_t* head_bin;    // [T]  bin of the tile's first cell
+    int32_t* tail_bin;    // [T]  bin of the tile's last cell
+    uint32_t* rec_first;  // [2][T]  cell range of the tile's head bin, then of its tail bin
     uint32_t* rec_last;   // [2][T]
-    double* rec_sum;      // [2][M][T]
-    float* rec_min;       // [2][M][T]
-    float* rec_max;       // [2][M][T]
     double* scal;         // [0] F_tot, [1] degenerate (0/1)
     float* fstore;        // [n_pad] importance of every cell, or NULL (see wants_fstore)
 };
@@ -122,11 +119,19 @@ struct BatchDev {
     int max_req_job;          // most requests in one job
 };
 
+// The descriptor layout a translation unit was compiled with.  The host
+// code that writes the descriptors and every unit whose kernels read them
+// must agree; launch_batch refuses a mismatch (objects built from different
+// versions of this header) before any kernel runs.
+constexpr uint64_t kDescriptorLayout =
+    ((uint64_t)sizeof(ReqDev) << 40) | ((uint64_t)sizeof(JobDev) << 20) | (uint64_t)sizeof(BatchDev);
+
 // Launch the five phases for the batch described by `b` (descriptors already
 // resident on the device).  `max_m`, `max_req`: largest field count and
-// requests per job in the batch.  ev (optional): kPhases + 1 events.
+// requests per job in the batch.  `layout`: the caller's kDescriptorLayout.
+// ev (optional): kPhases + 1 events.
 dvl_status launch_batch(const BatchDev& b, int dtype, int max_m, int max_req, int n_cu, hipStream_t s,
-                        hipEvent_t* ev = nullptr);
+                        uint64_t layout, hipEvent_t* ev = nullptr);
 
 // TF entry of every cell of one sorted field under quantiser (s, b) with
 // n_tf <= 256 entries, one byte per cell, over all n_pad (padded) cells.

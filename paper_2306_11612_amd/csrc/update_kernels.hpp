@@ -375,35 +375,75 @@ __global__ __launch_bounds__(kUpdThreads) void k_vmax_exact(BatchDev b) {
 
 // ------------------------------------------------------------------ K1
 
-// running sum of tile sums along a run, in the arithmetic of the scan mode
-struct RunAcc {
+// Error-free sum of two floats: s + e == a + b exactly (Knuth's TwoSum).
+__device__ __forceinline__ void two_sum_f(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// A sum kept in the arithmetic of the scan mode: fp64 (d), compensated fp32
+// (the unevaluated pair hi + lo) or plain fp32 (hi).  Used for the per-lane
+// tile partials and the running sum of tile sums along a run; the mode is
+// the same in every lane (a scalar branch).
+struct ModeSum {
     double d;
     float hi, lo;
     __device__ void init() { d = 0.0; hi = 0.0f; lo = 0.0f; }
     __device__ double value(int mode) const {
         return mode == DVL_SCAN_FP64 ? d : (mode == DVL_SCAN_KAHAN_FP32 ? (double)hi + (double)lo : (double)hi);
     }
-    __device__ void add(int mode, double x) {
+    __device__ void add_f(int mode, float x) {
         if (mode == DVL_SCAN_FP64) {
-            d += x;
+            d += (double)x;
         } else if (mode == DVL_SCAN_KAHAN_FP32) {
-            const float xf = (float)x;
-            const float s = hi + xf, bb = s - hi;
-            const float e = (hi - (s - bb)) + (xf - bb);
+            float s, e;
+            two_sum_f(hi, x, s, e);
             const float l = lo + e;
             hi = s + l;
             lo = l - (hi - s);
         } else {
-            hi += (float)x;
+            hi += x;
+        }
+    }
+    // add another sum of the same mode
+    __device__ void add(int mode, const ModeSum& o) {
+        if (mode == DVL_SCAN_FP64) {
+            d += o.d;
+        } else if (mode == DVL_SCAN_KAHAN_FP32) {
+            float s, e;
+            two_sum_f(hi, o.hi, s, e);
+            const float l = (lo + o.lo) + e;
+            hi = s + l;
+            lo = l - (hi - s);
+        } else {
+            hi += o.hi;
+        }
+    }
+    // the same total in every lane (butterfly; each combine is symmetric in
+    // its two operands, so every lane computes the same bits)
+    __device__ void wave_total(int mode) {
+        if (mode == DVL_SCAN_FP64) {
+            d = wave_sum_d(d);
+            return;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const int src = (lane_id() ^ o) << 2;
+            ModeSum x;
+            x.hi = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(hi)));
+            x.lo = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(lo)));
+            add(mode, x);
         }
     }
 };
 
 // One wave's run r of job j: stream its cells once (values, or cached
-// entries), evaluate f for every request of the job, sum f over each tile in
-// fp64 (per lane, 4 cells per step as (f0 + f1) + (f2 + f3), then the wave)
-// and record, per request and tile, the non-decreasing sum of the earlier
-// tiles of the run.  Both sources give the same f bit for bit.
+// entries), evaluate f for every request of the job, sum f over each tile
+// (per lane, 4 cells per step as (f0 + f1) + (f2 + f3) in fp32, accumulated
+// over the tile's steps and then over the wave in the request's scan
+// arithmetic: fp64, compensated fp32 or plain fp32) and record, per request
+// and tile, the non-decreasing sum of the earlier tiles of the run.  Both
+// sources give the same f bit for bit.
 template <int MT, int KR, typename D, bool P1>
 __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j, int64_t r, const float* tf_lds) {
     constexpr int G = Group<D>::n;
@@ -421,8 +461,8 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
     const int nsteps = (int)((c_end - c_begin + kStepCells - 1) / kStepCells);
 
     ImpCtx ctx[KR];
-    RunAcc run[KR];
-    double prev[KR], tacc[KR];
+    ModeSum run[KR], tacc[KR];
+    double prev[KR];
     int toff[KR], off[KR][MT], mode[KR];
     float* fst[KR];                   // where f of every cell is kept for the projection, or NULL
     double* lpre[KR];                 // the requests' in-run tile prefixes
@@ -444,7 +484,7 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
         }
         run[q].init();
         prev[q] = 0.0;
-        tacc[q] = 0.0;
+        tacc[q].init();
     }
     int64_t t = t_begin;
     int in_tile = 0;
@@ -480,18 +520,18 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
                         fv.w = f[3];
                         gstore<f32x4>(fst[q], quad, fv);
                     }
-                    tacc[q] += (double)((f[0] + f[1]) + (f[2] + f[3]));
+                    tacc[q].add_f(mode[q], (f[0] + f[1]) + (f[2] + f[3]));
                 }
             }
             if (++in_tile == tile_steps || s + g + 1 == nsteps) {
 #pragma unroll
                 for (int q = 0; q < KR; ++q) {
                     if (q < nreq) {
-                        const double ts = wave_sum_d(tacc[q]);
-                        tacc[q] = 0.0;
+                        tacc[q].wave_total(mode[q]);
                         prev[q] = fmax(prev[q], run[q].value(mode[q]));
                         if (lane == 0) gstore<double>(lpre[q], t, prev[q]);
-                        run[q].add(mode[q], ts);
+                        run[q].add(mode[q], tacc[q]);
+                        tacc[q].init();
                     }
                 }
                 ++t;
@@ -577,42 +617,6 @@ __global__ __launch_bounds__(kUpdThreads) void k_tile_sums(BatchDev b) {
 
 // ------------------------------------------------------------------ K3 helpers
 
-template <int MT>
-struct Seg {
-    double sum[MT];
-    float mn[MT];
-    float mx[MT];
-    uint32_t first;
-    uint32_t last;
-};
-
-template <int MT>
-__device__ __forceinline__ void seg_clear(Seg<MT>& s) {
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        s.sum[m] = 0.0;
-        s.mn[m] = INFINITY;
-        s.mx[m] = -INFINITY;
-    }
-    s.first = 0xFFFFFFFFu;
-    s.last = 0u;
-}
-
-// a precedes b in cell order
-template <int MT>
-__device__ __forceinline__ Seg<MT> seg_combine(const Seg<MT>& a, const Seg<MT>& b) {
-    Seg<MT> r;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        r.sum[m] = a.sum[m] + b.sum[m];
-        r.mn[m] = fminf(a.mn[m], b.mn[m]);
-        r.mx[m] = fmaxf(a.mx[m], b.mx[m]);
-    }
-    r.first = min(a.first, b.first);
-    r.last = max(a.last, b.last);
-    return r;
-}
-
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1)
         v = min(v, (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ o) << 2, (int)v));
@@ -643,140 +647,19 @@ __device__ __forceinline__ double tile_offset(const JobDev& j, const UpdWorkspac
     return fmin(fmax(lo + gload<double>(ws.local_prefix, t), lo), hi);
 }
 
-// Field statistics of the sorted cells [first, last] of one tile (tbase: its
-// first cell; view: its streams), computed by the whole wave from the stored
-// values of the partial 256-cell steps at its ends and the per-step
-// statistics of the steps it covers whole (at most tile_steps <= 64 of them,
-// one per lane).  Sums are fp64; every lane ends with the result.
-template <int MT, typename S>
-__device__ __forceinline__ void range_stats(const JobDev& j, int M, const RunView<MT>& view, int64_t tbase,
-                                            int64_t step0, uint32_t first, uint32_t last, double (&sum)[MT],
-                                            float (&mn)[MT], float (&mx)[MT]) {
-    const int lane = lane_id();
-    const int sf = (int)(((int64_t)first - tbase) >> 8), sl = (int)(((int64_t)last - tbase) >> 8);
-    const int64_t S_all = (int64_t)uni(j.n_tiles) * uni(j.tile_steps);
-    // end steps that the range covers whole are taken from their statistics
-    const bool starts = ((int64_t)first - tbase) % kStepCells == 0;
-    const bool ends = ((int64_t)last - tbase) % kStepCells == kStepCells - 1;
-    const bool head_whole = starts && (sl > sf || ends);
-    const bool tail_whole = ends && (sl > sf || starts);
-    const int a0 = head_whole ? sf : sf + 1;          // whole steps [a0, a1)
-    const int a1 = tail_whole ? sl + 1 : sl;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        sum[m] = 0.0;
-        mn[m] = INFINITY;
-        mx[m] = -INFINITY;
-    }
-    // the lane's 4 cells of a partial first step, then of a partial last step
-#pragma unroll
-    for (int end = 0; end < 2; ++end) {
-        if (end == 0 && head_whole) continue;
-        if (end == 1 && (sl == sf || tail_whole)) break;
-        const int st = end == 0 ? sf : sl;
-        const int64_t c = tbase + (int64_t)st * kStepCells + 4 * lane;
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            if (m < M) {
-                Quad<S> qd;
-                qd.load_at(view.base[m], (uint32_t)(st * kWave + lane) * Quad<S>::kBytes);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (c + k >= (int64_t)first && c + k <= (int64_t)last) {
-                        const float v = qd.get(k);
-                        sum[m] += (double)v;
-                        mn[m] = fminf(mn[m], v);
-                        mx[m] = fmaxf(mx[m], v);
-                    }
-                }
-            }
-        }
-    }
-    // whole steps
-    if (a0 + lane < a1) {
-        const int64_t gs = step0 + a0 + lane;
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            if (m < M) {
-                const int64_t o = (int64_t)m * S_all + gs;
-                sum[m] += gload<double>(j.step_sum, o);
-                mn[m] = fminf(mn[m], gload<float>(j.step_min, o));
-                mx[m] = fmaxf(mx[m], gload<float>(j.step_max, o));
-            }
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        if (m < M) {
-            sum[m] = wave_sum_d(sum[m]);
-            mn[m] = wave_min_f(mn[m]);
-            mx[m] = wave_max_f(mx[m]);
-        }
-    }
-}
-
-// Store bin `key` = cells [first, last] of tile t: a complete bin (dest 0)
-// gets its final mean, min, max and height; a tile-edge bin goes to the
-// tile's head (dest 1) or tail (dest 2) record, merged across tiles later.
-// tf: the request's tables (layout of its block).
-template <int MT, typename S>
-__device__ void close_bin(const ReqDev& q, const JobDev& j, int M, int64_t T, const RunView<MT>& view,
-                          int64_t tbase, int64_t step0, int dest, int64_t t, int key, uint32_t first,
-                          uint32_t last, const float* tf) {
-    double sm[MT];
-    float mn[MT], mx[MT];
-    range_stats<MT, S>(j, M, view, tbase, step0, first, last, sm, mn, mx);
-    const int lane = lane_id();
-    const uint32_t cnt = last - first + 1u;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        if (m < M && lane == m) {
-            if (dest == 0) {
-                const float mean = (float)(sm[m] / (double)cnt);
-                const int e = tf_entry(mean, q.s[m], q.b[m], q.nmax[m]);
-                const int64_t o = (int64_t)m * q.W + key;
-                gstore<float>(q.mean, o, mean);
-                gstore<float>(q.vmin, o, mn[m]);
-                gstore<float>(q.vmax, o, mx[m]);
-                gstore<float>(q.y, o, tf[q.tf_off[m] + e]);
-            } else {
-                const int64_t o = ((int64_t)(dest - 1) * M + m) * T + t;
-                gstore<double>(q.ws.rec_sum, o, sm[m]);
-                gstore<float>(q.ws.rec_min, o, mn[m]);
-                gstore<float>(q.ws.rec_max, o, mx[m]);
-            }
-        }
-    }
-    if (lane == 0) {
-        if (dest == 0) {
-            gstore<uint32_t>(q.first_cell, key, first);
-            gstore<uint32_t>(q.last_cell, key, last);
-        } else {
-            gstore<uint32_t>(q.ws.rec_first, (dest - 1) * T + t, first);
-            gstore<uint32_t>(q.ws.rec_last, (dest - 1) * T + t, last);
-        }
-    }
-}
-
-// a bin that holds one cell only (strictly inside a wide cell); called by the
-// lane owning cell g
-template <int MT, typename S>
-__device__ void write_single(const ReqDev& q, const JobDev& j, int M, int key, uint32_t g, const float* tf) {
-    gstore<uint32_t>(q.first_cell, key, g);
-    gstore<uint32_t>(q.last_cell, key, g);
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        if (m < M) {
-            Quad<S> qd;
-            qd.load(j.fields[m], (int64_t)(g >> 2));
-            const float x = qd.get((int)(g & 3u));
-            const int e = tf_entry(x, q.s[m], q.b[m], q.nmax[m]);
-            const int64_t o = (int64_t)m * q.W + key;
-            gstore<float>(q.mean, o, x);
-            gstore<float>(q.vmin, o, x);
-            gstore<float>(q.vmax, o, x);
-            gstore<float>(q.y, o, tf[q.tf_off[m] + e]);
-        }
+// Cell range [first, last] of bin `key` found in tile t: a bin that starts
+// and ends inside the tile (dest 0) is stored as the request's output; the
+// tile's first bin (dest 1) and last bin (dest 2) go to the tile's head and
+// tail records, merged across tiles by K4.  Called by the whole wave.
+__device__ __forceinline__ void close_bin(const ReqDev& q, int64_t T, int dest, int64_t t, int key,
+                                          uint32_t first, uint32_t last) {
+    if (lane_id() != 0) return;
+    if (dest == 0) {
+        gstore<uint32_t>(q.first_cell, key, first);
+        gstore<uint32_t>(q.last_cell, key, last);
+    } else {
+        gstore<uint32_t>(q.ws.rec_first, (dest - 1) * T + t, first);
+        gstore<uint32_t>(q.ws.rec_last, (dest - 1) * T + t, last);
     }
 }
 
@@ -846,14 +729,12 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
     const int tile_steps = uni(j.tile_steps);
     const int64_t tile_cells = (int64_t)tile_steps * kStepCells;
     const int64_t tbase = t * tile_cells;
-    const int64_t step0 = t * tile_steps;
     const int64_t tend = min(tbase + tile_cells, n);
     const uint32_t last_valid = (uint32_t)(tend - 1);
     const int nsteps = (int)((tend - tbase + kStepCells - 1) / kStepCells);
-    const RunView<MT> vals = run_view<MT, StepData<MT, S>>(j, M, tbase);
     RunView<MT> view;
     if constexpr (std::is_same<D, StepF<MT>>::value) {
-        view = vals;
+        view = run_view<MT, StepData<MT, S>>(j, M, tbase);
         view.base[0] = reinterpret_cast<const char*>(uni(q.ws.fstore)) + tbase * 4;
     } else {
         view = run_view<MT, D>(j, M, tbase);
@@ -963,15 +844,17 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
         const int key_last = full ? key_end : readlane(bhi_last, last_lane);
         // (1) the open bin ended with the previous step
         if (o_valid && key0 != O) {
-            close_bin<MT, S>(q, j, M, T, vals, tbase, step0, O == Bh ? 1 : 0, t, O, O_first, (uint32_t)(c0 - 1),
-                             tf_lds);
+            close_bin(q, T, O == Bh ? 1 : 0, t, O, O_first, (uint32_t)(c0 - 1));
             o_valid = false;
         }
         // (2) bins strictly inside a wide cell hold that cell alone
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (valid[k] && bhi[k] > blo[k] + 1)
-                for (int bb = blo[k] + 1; bb < bhi[k]; ++bb) write_single<MT, S>(q, j, M, bb, g[k], tf_lds);
+                for (int bb = blo[k] + 1; bb < bhi[k]; ++bb) {
+                    gstore<uint32_t>(q.first_cell, bb, g[k]);
+                    gstore<uint32_t>(q.last_cell, bb, g[k]);
+                }
         // (3) every bin that is the first or last bin of some cell of this
         //     step, in increasing order; all but the step's last one close
         int b = key0;
@@ -992,8 +875,7 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
                 o_valid = true;
                 break;
             }
-            close_bin<MT, S>(q, j, M, T, vals, tbase, step0, b == Bh ? 1 : 0, t, b, bfirst, wave_max_u32(gmax),
-                             tf_lds);
+            close_bin(q, T, b == Bh ? 1 : 0, t, b, bfirst, wave_max_u32(gmax));
             o_valid = false;
             int nk = INT_MAX;
 #pragma unroll
@@ -1014,7 +896,7 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
 
     // tile end: the open bin is the tile's last bin
     if (o_valid) {
-        close_bin<MT, S>(q, j, M, T, vals, tbase, step0, O == Bh ? 1 : 2, t, O, O_first, last_valid, tf_lds);
+        close_bin(q, T, O == Bh ? 1 : 2, t, O, O_first, last_valid);
         if (lane == 0) {
             gstore<int32_t>(q.ws.head_bin, t, Bh);
             gstore<int32_t>(q.ws.tail_bin, t, O);
@@ -1057,12 +939,209 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
     }
 }
 
+// ------------------------------------------------------------------ K4
+
+// First index in [0, T) where `pred` turns false (pred true on a prefix, false
+// after), found by the whole wave: each round the 64 lanes probe 64 evenly
+// spaced points of the remaining range, so three or four rounds of loads
+// replace the ~17 dependent loads of a binary search over 10^5 tiles.
+template <typename Pred>
+__device__ __forceinline__ int64_t wave_partition_point(int64_t T, Pred pred) {
+    const int lane = lane_id();
+    int64_t lo = 0, hi = T;          // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const int64_t step = (hi - lo + kWave - 1) / kWave;
+        const int64_t p = lo + step * lane;
+        const bool t = p < hi && pred(p);
+        const int c = __popcll(__ballot(t));          // lanes 0 .. c-1 hold true
+        if (c == 0) return lo;                       // pred(lo) is false
+        const int64_t new_lo = lo + step * (c - 1) + 1;
+        hi = min(hi, lo + step * c);
+        lo = new_lo;
+    }
+    return lo;
+}
+
+// Field statistics of the sorted cells [first, last], by one wave: the stored
+// values of the partial 256-cell steps at the two ends, the per-step
+// statistics of the whole steps next to them and the per-tile statistics of
+// the whole tiles in between (a step or tile is whole when the range holds
+// all of its cells below n).  Sums are fp64; every lane ends with the result.
+template <int MT, typename S>
+__device__ __forceinline__ void bin_range_stats(const JobDev& j, int M, uint32_t first, uint32_t last,
+                                                double (&sum)[MT], float (&mn)[MT], float (&mx)[MT]) {
+    const int lane = lane_id();
+    const int64_t n = uni(j.n);
+    const int ts = uni(j.tile_steps);
+    const int64_t T = uni(j.n_tiles);
+    const int64_t S_all = T * ts;
+    const int64_t f = first, l = last;
+    auto whole_step = [&](int64_t st) { return f <= st * kStepCells && l >= min(n, st * kStepCells + kStepCells) - 1; };
+    const int64_t sf = f / kStepCells, sl = l / kStepCells;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        sum[m] = 0.0;
+        mn[m] = INFINITY;
+        mx[m] = -INFINITY;
+    }
+    // partial end steps: each lane its 4 cells
+    const bool wf = whole_step(sf), wl = whole_step(sl);
+#pragma unroll
+    for (int end = 0; end < 2; ++end) {
+        if (end == 0 && wf) continue;
+        if (end == 1 && (sl == sf || wl)) break;
+        const int64_t st = end == 0 ? sf : sl;
+        const int64_t c = st * kStepCells + 4 * lane;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            if (m < M) {
+                Quad<S> qd;
+                qd.load(j.fields[m], st * kWave + lane);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (c + k >= f && c + k <= l) {
+                        const float v = qd.get(k);
+                        sum[m] += (double)v;
+                        mn[m] = fminf(mn[m], v);
+                        mx[m] = fmaxf(mx[m], v);
+                    }
+                }
+            }
+        }
+    }
+    // whole steps [a, b]; whole tiles [ta, tb] among them
+    const int64_t a = wf ? sf : sf + 1, b = wl ? sl : sl - 1;
+    if (a <= b) {
+        const int64_t ta = (a + ts - 1) / ts, tb = (b + 1) / ts - 1;
+        int64_t s0 = a, s1 = b, s2 = 1, s3 = 0;       // step ranges [s0, s1] and [s2, s3] outside whole tiles
+        if (ta <= tb) {
+            s1 = ta * ts - 1;
+            s2 = (tb + 1) * ts;
+            s3 = b;
+            for (int64_t t = ta + lane; t <= tb; t += kWave) {
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    if (m < M) {
+                        const int64_t o = (int64_t)m * T + t;
+                        sum[m] += gload<double>(j.agg_sum, o);
+                        mn[m] = fminf(mn[m], gload<float>(j.agg_min, o));
+                        mx[m] = fmaxf(mx[m], gload<float>(j.agg_max, o));
+                    }
+                }
+            }
+        }
+        const int64_t n0 = s1 >= s0 ? s1 - s0 + 1 : 0, n1 = s3 >= s2 ? s3 - s2 + 1 : 0;
+        for (int64_t i = lane; i < n0 + n1; i += kWave) {
+            const int64_t st = i < n0 ? s0 + i : s2 + (i - n0);
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                if (m < M) {
+                    const int64_t o = (int64_t)m * S_all + st;
+                    sum[m] += gload<double>(j.step_sum, o);
+                    mn[m] = fminf(mn[m], gload<float>(j.step_min, o));
+                    mx[m] = fmaxf(mx[m], gload<float>(j.step_max, o));
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        if (m < M) {
+            sum[m] = wave_sum_d(sum[m]);
+            mn[m] = wave_min_f(mn[m]);
+            mx[m] = wave_max_f(mx[m]);
+        }
+    }
+}
+
+// K4: one wave per (request, bin).  The bin's cell range: written by the
+// rescan when the bin starts and ends inside one rescanned tile; else the
+// smallest first and largest last cell over the records of the tiles it
+// touches (a tile inside one bin is that bin's record whole, a rescanned
+// tile holds records of its first and last bin).  Then the statistics of the
+// range and the height of the mean.
+template <int MT, typename S>
+__global__ __launch_bounds__(256) void k_bin_stats(BatchDev bd) {
+    const int lane = lane_id();
+    const int64_t u = (int64_t)block_x() * (256 / kWave) + thread_x() / kWave;
+    if (u >= bd.k4_units) return;   // the whole wave
+    const int qi = uni(find_req_k4(bd, u));
+    const ReqDev& q = bd.reqs[qi];
+    const JobDev& j = bd.jobs[uni(q.job)];
+    const int M = uni(fields_of<MT>(j.M));
+    const int b = (int)(u - uni(q.k4_unit0));
+    if (b == 0 && lane == 0) {
+        gstore<double>(q.f_total, 0, gload<double>(q.ws.scal, 0));
+        gstore<float>(q.vmax_used, 0, gload<float>(q.vmax_dev, 0));
+    }
+    const int64_t T = uni(j.n_tiles);
+    const int32_t* hb = q.ws.head_bin;
+    const int32_t* tb = q.ws.tail_bin;
+    // tiles touching bin b: t0 = first with tail >= b, t1 = last with head <= b
+    const int64_t t0 = wave_partition_point(T, [&](int64_t t) { return gload<int32_t>(tb, t) < b; });
+    const int64_t t1 = wave_partition_point(T, [&](int64_t t) { return gload<int32_t>(hb, t) <= b; }) - 1;
+    uint32_t first = 0xFFFFFFFFu, last = 0u;
+    bool inside = false;
+    if (t0 == t1) {
+        const int h0 = gload<int32_t>(hb, t0), e0 = gload<int32_t>(tb, t0);
+        inside = h0 < b && b < e0;
+    }
+    if (inside) {
+        first = gload<uint32_t>(q.first_cell, b);
+        last = gload<uint32_t>(q.last_cell, b);
+    } else {
+        for (int64_t t = t0 + lane; t <= t1; t += kWave) {
+            const int r = gload<int32_t>(hb, t) == b ? 0 : (gload<int32_t>(tb, t) == b ? 1 : -1);
+            if (r < 0) continue;
+            first = min(first, gload<uint32_t>(q.ws.rec_first, r * T + t));
+            last = max(last, gload<uint32_t>(q.ws.rec_last, r * T + t));
+        }
+        first = wave_min_u32(first);
+        last = wave_max_u32(last);
+    }
+    // no cell (cannot happen with a positive total width); a range outside
+    // the volume is treated the same way, so no statistic reads past it
+    if (first == 0xFFFFFFFFu || first > last || (int64_t)last >= uni(j.n)) {
+        if (lane == 0) {
+            gstore<uint32_t>(q.first_cell, b, 0xFFFFFFFFu);
+            gstore<uint32_t>(q.last_cell, b, 0xFFFFFFFEu);
+        }
+        if (lane < M) {
+            const int64_t o = (int64_t)lane * q.W + b;
+            gstore<float>(q.mean, o, 0.0f);
+            gstore<float>(q.vmin, o, INFINITY);
+            gstore<float>(q.vmax, o, -INFINITY);
+            gstore<float>(q.y, o, 0.0f);
+        }
+        return;
+    }
+    double sm[MT];
+    float mn[MT], mx[MT];
+    bin_range_stats<MT, S>(j, M, first, last, sm, mn, mx);
+    if (lane == 0 && !inside) {
+        gstore<uint32_t>(q.first_cell, b, first);
+        gstore<uint32_t>(q.last_cell, b, last);
+    }
+    const uint32_t cnt = last - first + 1u;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        if (m < M && lane == m) {
+            const float mean = (float)(sm[m] / (double)cnt);
+            const int e = tf_entry(mean, q.s[m], q.b[m], q.nmax[m]);
+            const int64_t o = (int64_t)m * q.W + b;
+            gstore<float>(q.mean, o, mean);
+            gstore<float>(q.vmin, o, mn[m]);
+            gstore<float>(q.vmax, o, mx[m]);
+            gstore<float>(q.y, o, gload<float>(q.tf, q.tf_off[m] + e));
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launcher
 
 // launchers of the kernels that do not depend on the storage type (update.hip)
 dvl_status launch_carry(const BatchDev& b, hipStream_t s);
 dvl_status launch_classify(const BatchDev& b, hipStream_t s);
-dvl_status launch_edges(const BatchDev& b, int mt, hipStream_t s);
 
 template <int MT, typename S, int KR>
 static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEvent_t* ev) {
@@ -1112,33 +1191,51 @@ static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEv
         DVL_HIP(hipGetLastError());
     }
     if (dvl_status st = mark(4)) return st;
-    if (dvl_status st = launch_edges(b, MT, s)) return st;
+    {
+        const unsigned g4 = (unsigned)std::max<int64_t>(1, (b.k4_units + 3) / 4);
+        hipLaunchKernelGGL((k_bin_stats<MT, S>), dim3(g4), dim3(256), 0, s, b);
+        DVL_HIP(hipGetLastError());
+    }
     return mark(5);
 }
+
+// One storage type and field count (both request-count variants).  Each
+// (S, MT) pair is instantiated in a translation unit of its own, generated by
+// the build (the fifteen compile in parallel); elsewhere the declarations
+// below keep the compiler from instantiating them.
+template <typename S, int MT>
+dvl_status launch_sm(const BatchDev& b, int max_req, int n_cu, hipStream_t s, uint64_t layout, hipEvent_t* ev) {
+    if (layout != kDescriptorLayout) {
+        set_error("descriptor layout mismatch between library objects (%llx vs %llx): rebuild the library",
+                  (unsigned long long)layout, (unsigned long long)kDescriptorLayout);
+        return DVL_E_INVALID;
+    }
+    if (max_req <= 1) return launch_typed<MT, S, 1>(b, n_cu, s, ev);
+    return launch_typed<MT, S, kMaxReqPerJob>(b, n_cu, s, ev);
+}
+
+#define DVL_FOR_EACH_LAUNCH(X) \
+    X(F32, 1) X(F32, 2) X(F32, 4) X(F32, 8) X(F32, 16) \
+    X(F16, 1) X(F16, 2) X(F16, 4) X(F16, 8) X(F16, 16) \
+    X(BF16, 1) X(BF16, 2) X(BF16, 4) X(BF16, 8) X(BF16, 16)
+#define DVL_EXTERN_LAUNCH(S, MT) \
+    extern template dvl_status launch_sm<S, MT>(const BatchDev&, int, int, hipStream_t, uint64_t, hipEvent_t*);
+DVL_FOR_EACH_LAUNCH(DVL_EXTERN_LAUNCH)
+#undef DVL_EXTERN_LAUNCH
 
 // Field-count variants: batches whose jobs all have 1, 2, 4 or 8 fields run
 // the variant with that count fixed at compile time; others (mixed counts,
 // 3, 5-7 or more than 8 fields) the general variant, which reads M per job.
-template <typename S, int KR>
-static dvl_status launch_m(const BatchDev& b, int max_m, int n_cu, hipStream_t s, hipEvent_t* ev) {
+template <typename S>
+static dvl_status launch_s(const BatchDev& b, int max_m, int max_req, int n_cu, hipStream_t s, uint64_t layout,
+                           hipEvent_t* ev) {
     switch (max_m) {
-        case 1: return launch_typed<1, S, KR>(b, n_cu, s, ev);
-        case 2: return launch_typed<2, S, KR>(b, n_cu, s, ev);
-        case 4: return launch_typed<4, S, KR>(b, n_cu, s, ev);
-        case 8: return launch_typed<8, S, KR>(b, n_cu, s, ev);
-        default: return launch_typed<16, S, KR>(b, n_cu, s, ev);
+        case 1: return launch_sm<S, 1>(b, max_req, n_cu, s, layout, ev);
+        case 2: return launch_sm<S, 2>(b, max_req, n_cu, s, layout, ev);
+        case 4: return launch_sm<S, 4>(b, max_req, n_cu, s, layout, ev);
+        case 8: return launch_sm<S, 8>(b, max_req, n_cu, s, layout, ev);
+        default: return launch_sm<S, 16>(b, max_req, n_cu, s, layout, ev);
     }
 }
-
-template <typename S>
-static dvl_status launch_s(const BatchDev& b, int max_m, int max_req, int n_cu, hipStream_t s, hipEvent_t* ev) {
-    if (max_req <= 1) return launch_m<S, 1>(b, max_m, n_cu, s, ev);
-    return launch_m<S, kMaxReqPerJob>(b, max_m, n_cu, s, ev);
-}
-
-// one per storage type, each in its own translation unit (update_<type>.hip)
-dvl_status launch_batch_f32(const BatchDev& b, int max_m, int max_req, int n_cu, hipStream_t s, hipEvent_t* ev);
-dvl_status launch_batch_f16(const BatchDev& b, int max_m, int max_req, int n_cu, hipStream_t s, hipEvent_t* ev);
-dvl_status launch_batch_bf16(const BatchDev& b, int max_m, int max_req, int n_cu, hipStream_t s, hipEvent_t* ev);
 
 }  // namespace dvl

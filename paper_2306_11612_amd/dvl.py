@@ -382,7 +382,7 @@ class Volume:
         n = C.c_int32()
         _check(lib().dvl_kernel_times(self.handle, ms.ctypes.data_as(C.c_void_p), C.byref(n)),
                "dvl_kernel_times")
-        names = ("vmax_exact", "tile_sums", "carry", "bin", "edges")
+        names = ("vmax_exact", "tile_sums", "carry", "bin", "bin_stats")
         return dict(zip(names, ms.tolist())), int(n.value)
 
     def close(self):
@@ -469,7 +469,7 @@ class Executor:
         n = C.c_int32()
         _check(lib().dvl_executor_kernel_times(self.handle, ms.ctypes.data_as(C.c_void_p), C.byref(n)),
                "dvl_executor_kernel_times")
-        names = ("vmax_exact", "tile_sums", "carry", "bin", "edges")
+        names = ("vmax_exact", "tile_sums", "carry", "bin", "bin_stats")
         return dict(zip(names, ms.tolist())), int(n.value)
 
     def close(self):

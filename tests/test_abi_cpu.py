@@ -34,7 +34,9 @@ def test_host_only_entry_points():
     assert st == dvl.E_INVALID
     assert L.dvl_update_workspace_bytes(0, 4, 10) == 0
     w = L.dvl_update_workspace_bytes(500_000_000, 4, 1920)
-    assert 10e6 < w < 40e6          # per-tile records, independent of W
+    # per tile: prefixes, bin indices and cell-range records (48 B), whatever W and M
+    assert 3e6 < w < 12e6
+    assert L.dvl_update_workspace_bytes(500_000_000, 16, 1920) == w
     assert L.dvl_num_cells(None) == 0
     L.dvl_destroy(None)
 
