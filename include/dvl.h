@@ -249,6 +249,31 @@ typedef struct {
 dvl_status dvl_update(dvl_volume* v, const dvl_params* p, const dvl_bins* out, void* stream);
 
 /* ---------------------------------------------------------------------
+ * dvl_update_noalloc -- dvl_update for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results (bitwise the same as
+ * dvl_update) and asynchrony; it calls no allocator and no hipMalloc.
+ *
+ * Its descriptors and workspace live in one fixed device scratch array of
+ * dvl_update_noalloc_max_bytes() bytes (64 MiB) per device, held from the
+ * first call on that device until the process ends; the descriptors are
+ * written by kernels (no memcpy, no memset).  A volume fits when 72 bytes
+ * per 4096-cell tile plus about 24 KB stay within it (about 3.8e9 cells,
+ * whatever the field count); larger ones get DVL_E_NOMEM with a message and
+ * nothing is enqueued.  It never stores f for the projection and never
+ * builds the TF entry cache: it reads the cache only when the cache already
+ * holds this update's windows and the volume was updated on this stream
+ * before.  Every call on a device shares that device's scratch, which keeps
+ * the last call's contents: calls that overlap on one device (other streams,
+ * other threads) race, so the caller orders them (one stream).  The
+ * volume's device must be current.  Errors: as dvl_update, and
+ * DVL_E_INVALID when another device is current.
+ * ------------------------------------------------------------------- */
+dvl_status dvl_update_noalloc(dvl_volume* v, const dvl_params* p, const dvl_bins* out, void* stream);
+/* size of the per-device scratch of dvl_update_noalloc */
+size_t dvl_update_noalloc_max_bytes(void);
+
+/* ---------------------------------------------------------------------
  * Batched updates (many volumes and TF requests in one launch per phase).
  * Each request is the update of Eqs. 1-4 and section Projecting Cells to 1D
  * (as dvl_update); the paper issued one CUDA stream per field and found no

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1174,6 +1175,127 @@ dvl_status dvl_update(dvl_volume* v, const dvl_params* p, const dvl_bins* out, v
     if (st == DVL_E_HIP) v->sticky = st;
     return st;
 }
+
+// ------------------------------------------------------------------ allocation-free update
+
+}  // extern "C"
+
+namespace dvl {
+
+// The fixed device scratch of dvl_update_noalloc: the descriptor block
+// (descriptors, tables, rescan queues) followed by the request workspace.
+// Every call on a device shares its copy.  In host code `scratch` names a
+// host-side stand-in, never the device memory: its device address comes
+// from hipGetSymbolAddress, once per device, and only that address is used.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_dev[kMaxDevices] = {};
+
+// device address of this device's scratch (the device must be current)
+static dvl_status scratch_address(int dev, char** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) return fail(DVL_E_INVALID, "device %d outside [0, %d)", dev, kMaxDevices);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[dev] = (char*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return DVL_OK;
+}
+
+// Upload of a host image into device memory through kernel arguments (the
+// runtime copies them at launch): no staging buffer, no memcpy node.
+constexpr int kPokeWords = 768;
+struct PokeArgs {
+    uint32_t* dst;
+    uint32_t n;
+    uint32_t w[kPokeWords];
+};
+
+__global__ __launch_bounds__(256) void k_poke(PokeArgs a) {
+    for (uint32_t i = threadIdx.x; i < a.n; i += blockDim.x) a.dst[i] = a.w[i];
+}
+
+static dvl_status poke(char* dst, const char* src, size_t bytes, hipStream_t s) {
+    const size_t nw = bytes / 4;
+    PokeArgs a;
+    for (size_t i = 0; i < nw; i += kPokeWords) {
+        a.dst = reinterpret_cast<uint32_t*>(dst) + i;
+        a.n = (uint32_t)std::min<size_t>(kPokeWords, nw - i);
+        memcpy(a.w, src + 4 * i, (size_t)a.n * 4);
+        hipLaunchKernelGGL(k_poke, dim3(1), dim3(256), 0, s, a);
+        DVL_HIP(hipGetLastError());
+    }
+    return DVL_OK;
+}
+
+// A job reads the volume's entry cache here only when the cache already holds
+// its key (it is never built here) and this stream already has a reader
+// event of the volume (re-recorded below), so a later rebuild elsewhere
+// still waits for this launch.
+static void use_existing_cache(Plan& P, hipStream_t s) {
+    for (JobDev& j : P.jobs) {
+        for (int m = 0; m < kMaxFields; ++m) j.idx[m] = nullptr;
+        dvl_volume* v = P.reqs[j.req0].v;
+        if (v->idx_policy == DVL_ENTRY_CACHE_NEVER || !v->idx_valid) continue;
+        CacheKey key;
+        if (!key_of(P.reqs[j.req0], key) || !(key == v->idx_key)) continue;
+        bool reader = false;
+        for (auto& r : v->cache_readers) reader = reader || r.first == s;
+        if (!reader) continue;
+        for (int m = 0; m < v->M; ++m) j.idx[m] = v->idx_s[m];
+    }
+}
+
+}  // namespace dvl
+
+extern "C" {
+
+dvl_status dvl_update_noalloc(dvl_volume* v, const dvl_params* p, const dvl_bins* out, void* stream) {
+    g_err.clear();
+    std::vector<ReqHost> reqs(1);
+    if (dvl_status st = volume_request(v, p, out, reqs[0])) return st;
+    int dev = -1;
+    DVL_HIP(hipGetDevice(&dev));
+    if (dev != v->device) return fail(DVL_E_INVALID, "volume lives on device %d, device %d is current", v->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+    Plan P;
+    if (dvl_status st = plan_batch(std::move(reqs), P)) return st;
+    const size_t block = al256(P.device_bytes);
+    const size_t need = block + workspace_bytes(v->n_tiles, v->M, 0);
+    if (need > kScratchBytes)
+        return fail(DVL_E_NOMEM, "this update needs %zu bytes of scratch; dvl_update_noalloc has %zu "
+                    "(use dvl_update)", need, kScratchBytes);
+    char* base = nullptr;
+    if (dvl_status st = scratch_address(dev, &base)) return st;
+    workspace_carve(base + block, v->n_tiles, v->M, 0, &P.rdev[0].ws);
+    use_existing_cache(P, s);
+    if (dvl_status st = cache_wait(P, s)) return st;
+    std::vector<char> img(P.block_bytes);
+    if (dvl_status st = fill_block(P, img.data(), base)) return st;
+    if (dvl_status st = poke(base, img.data(), P.block_bytes, s)) {
+        v->sticky = st;
+        return st;
+    }
+    int paths = 0;
+    for (const JobDev& j : P.jobs) paths |= j.idx[0] ? kPathEntries : kPathValues;
+    if (dvl_status st = launch_batch(batch_dev(P, base, paths), P.dtype, P.max_m, P.max_req, v->n_cu, s, kDescriptorLayout, nullptr)) {
+        if (st == DVL_E_HIP) v->sticky = st;
+        return st;
+    }
+    for (JobDev& j : P.jobs)
+        if (j.idx[0])
+            for (auto& r : P.reqs[j.req0].v->cache_readers)
+                if (r.first == s) DVL_HIP(hipEventRecord(r.second, s));
+    return DVL_OK;
+}
+
+size_t dvl_update_noalloc_max_bytes(void) { return kScratchBytes; }
 
 dvl_status dvl_read_bins(const dvl_volume* v, const dvl_bins* b, int32_t W, void* stream, uint32_t* count,
                          uint32_t* first, uint32_t* last, float* mean, float* vmin, float* vmax, float* y,

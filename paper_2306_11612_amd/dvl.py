@@ -130,6 +130,8 @@ def lib():
         "dvl_field_range": (i32, [vp, i32, C.POINTER(f32), C.POINTER(f32)]),
         "dvl_set_tf": (i32, [vp, i32, vp, i32, f32, f32]),
         "dvl_update": (i32, [vp, C.POINTER(dvl_params), C.POINTER(dvl_bins), vp]),
+        "dvl_update_noalloc": (i32, [vp, C.POINTER(dvl_params), C.POINTER(dvl_bins), vp]),
+        "dvl_update_noalloc_max_bytes": (C.c_size_t, []),
         "dvl_read_bins": (i32, [vp, C.POINTER(dvl_bins), i32, vp] + [vp] * 9),
         "dvl_export_order": (i32, [vp, vp, vp, vp]),
         "dvl_export_sorted": (i32, [vp, vp, vp, vp]),
@@ -263,6 +265,14 @@ def update(vol: "Volume", p: dvl_params, bins: Bins, stream=None):
     """dvl_update: enqueue one update on the stream."""
     b = bins.struct()
     _check(lib().dvl_update(vol.handle, C.byref(p), C.byref(b), _stream_ptr(stream)), "dvl_update")
+
+
+def update_noalloc(vol: "Volume", p: dvl_params, bins: Bins, stream=None):
+    """dvl_update_noalloc: the update through the library's fixed device
+    scratch (no device allocation)."""
+    b = bins.struct()
+    _check(lib().dvl_update_noalloc(vol.handle, C.byref(p), C.byref(b), _stream_ptr(stream)),
+           "dvl_update_noalloc")
 
 
 def read_bins(vol: "Volume", bins: Bins, stream=None) -> dict:
