@@ -140,13 +140,19 @@ def bench_batch32(args, dt):
     from synth.configs import config_seed
     from paper_2306_11612_amd import dvl
 
+    from paper_2306_11612_amd import tune
     W, n_vol = 2048, 32
     t0 = time.perf_counter()
-    vols = []
+    vols, layouts = [], []
     for k in range(n_vol):
         v = synth.cfg4_volume(k, "cuda", n_vol)
         fields = [f.to(dt) for f in v.fields]
-        vols.append(dvl.build_order(v.x, v.y, v.z, v.level, fields))
+        # the layout autotuner (cached per shape class: cell count and width
+        # rounded to powers of two, field count, storage)
+        lay = tune.best_layout(v.x, v.y, v.z, v.level, fields, W)
+        layouts.append((lay["tile_steps"], lay["run_waves"]))
+        vols.append(dvl.build_order(v.x, v.y, v.z, v.level, fields, tile_steps=lay["tile_steps"],
+                                    run_waves=lay["run_waves"]))
         del v, fields
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -204,11 +210,25 @@ def bench_batch32(args, dt):
         g.launch()
     ms_graph = timed(graph, "captured graph")
     cached = all(V.entry_cache_info() is not None for V in vols)
+    dom = max(("tile_sums", "bin", "bin_stats"), key=lambda k: per_launch[k])
     elem = 4 if args.dtype == "f32" else 2
     segs = [V.level_segments() for V in vols]
     lbpc = sum(nm * 64 + (ns // 4) * 4 for ns, nm in segs) / cells   # level codes + mixed segments
     bpc = (M + lbpc) if cached else (M * elem + lbpc)
-    achieved = cells * bpc / (per_launch["tile_sums"] * 1e-3) / 1e9
+    # algorithmic bytes per launch of each candidate dominant kernel:
+    #  tile_sums  every cell's M entries (or values) + level stream
+    #  bin        the rescanned tiles (at most min(T, W) per volume); with
+    #             W >= T / 4 the importance pass stored f, which the rescan
+    #             reads (4 B per cell), else it reads what the first pass read
+    #  bin_stats  per bin, the values of its two partial end steps
+    kbytes = {"tile_sums": cells * bpc, "bin": 0.0, "bin_stats": 0.0}
+    for V, (ts, _) in zip(vols, layouts):
+        tile_cells = 256 * ts
+        T = -(-V.n // tile_cells)
+        stored_f = W * 4 >= T
+        kbytes["bin"] += min(T, W) * tile_cells * (4 if stored_f else bpc)
+        kbytes["bin_stats"] += W * 2 * 256 * M * elem
+    achieved = kbytes[dom] / (per_launch[dom] * 1e-3) / 1e9
     ms_best = min(ms_batch, ms_graph)
     out = {
         "metric": METRIC, "value": cells / (ms_best * 1e-3), "unit": "cells/s", "n_gpus": 1,
@@ -217,10 +237,17 @@ def bench_batch32(args, dt):
         "config": {"workload": "batch32: 32 AMR volumes of 1-20 M cells (log-uniform), 2-4 levels, 8 fields, "
                                "one TF change per volume per step", "n_volumes": n_vol, "n_cells": cells,
                    "n_fields": M, "n_bins": W, "exponent": args.exponent, "min_importance": args.min_importance},
-        "roofline": {"bound": "hbm", "kernel": "tile_sums" + ("[entries]" if cached else ""),
+        "roofline": {"bound": "hbm", "kernel": dom + ("[entries]" if cached and dom == "tile_sums" else ""),
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "bytes_per_launch": cells * bpc,
-                     "bytes_per_cell": bpc, "avg_launch_ms": per_launch["tile_sums"]},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "bytes_per_launch": kbytes[dom],
+                     "bytes_per_cell": kbytes[dom] / cells, "avg_launch_ms": per_launch[dom],
+                     "byte_model": {"tile_sums": "M cached entry bytes (or M field values) + level stream per cell",
+                                    "bin": "rescanned tiles: stored f (4 B per cell) or the first pass's bytes",
+                                    "bin_stats": "per bin: the values of its two partial end steps"}[dom],
+                     "kernel_bytes": kbytes},
+        "dominant_kernel": dom,
+        "tuned_layouts": {f"tile_steps={a},run_waves={b or 'default'}": layouts.count((a, b))
+                          for a, b in sorted(set(layouts))},
         "entry_cache": cached,
         "sequential_ms_per_step": ms_seq, "batch_ms_per_step": ms_batch, "graph_ms_per_step": ms_graph,
         "speedup_vs_sequential": ms_seq / ms_best,

@@ -358,6 +358,76 @@ dvl_status dvl_export_sorted(const dvl_volume* v, uint8_t* level, void* const* f
                              void* stream);
 
 /* ---------------------------------------------------------------------
+ * Brushing and linking (section Brushing and Linking): a region of interest
+ * selected in the 1D plot travels to the 3D view as the first and last
+ * Hilbert codes of its cells, and a cell sampled in 3D is highlighted when
+ * its own Hilbert code lies in such a range.
+ *
+ * dvl_select_bins: the cells of bins b0..b1 of an update's outputs `bins`
+ * (n_bins = W, 0 <= b0 <= b1 < W) are the sorted cells first..last
+ * (first = first_cell[b0], last = last_cell[b1]); key_lo/key_hi are their
+ * Hilbert keys (keys increase along the sorted order, so every cell of the
+ * region has a key in [key_lo, key_hi] and no other cell does).  Host
+ * outputs, any may be NULL; synchronises `stream` (after the update on it).
+ * Errors: DVL_E_INVALID, DVL_E_STATE (bins not of this volume), DVL_E_HIP.
+ *
+ * dvl_select_mask: mask[i] = 1 for every cell i (ORIGINAL order) whose key
+ * lies in one of the n_ranges closed ranges ranges[2k] .. ranges[2k + 1]
+ * (host uint64 pairs, 1 <= n_ranges <= 128, copied), else 0.  mask: device
+ * uint8[n_cells], caller-owned.  Asynchronous.
+ * ------------------------------------------------------------------- */
+dvl_status dvl_select_bins(const dvl_volume* v, const dvl_bins* bins, int32_t n_bins, int32_t b0, int32_t b1,
+                           void* stream, uint32_t* first, uint32_t* last, uint64_t* key_lo, uint64_t* key_hi);
+dvl_status dvl_select_mask(const dvl_volume* v, const uint64_t* ranges, int32_t n_ranges, uint8_t* mask,
+                           void* stream);
+
+/* ---------------------------------------------------------------------
+ * dvl_zoom -- the zoom interaction proposed in the Conclusions: a new
+ * volume holding the sorted cells first..last of `v` (typically a region
+ * from dvl_select_bins), so that its volume line spends the whole plot width
+ * on them.  Cell i of the new volume is sorted cell first + i of `v`: that
+ * range is its original order (dvl_export_order returns the range's keys
+ * and the identity permutation; dvl_set_field takes values in that order).
+ * Levels, fields and keys are copied; data ranges and statistics are those
+ * of the range; no TF is set.  opt: layout options as for
+ * dvl_build_order_ex (NULL: defaults, and `v`'s allocator).  Synchronises
+ * `stream`.  Errors: DVL_E_INVALID, DVL_E_NOMEM, DVL_E_HIP.
+ * ------------------------------------------------------------------- */
+dvl_status dvl_zoom(const dvl_volume* v, uint32_t first, uint32_t last, const dvl_build_options* opt,
+                    void* stream, dvl_volume** out);
+
+/* ---------------------------------------------------------------------
+ * dvl_bin_histograms -- the histogram heatmap of volume-line plots
+ * (section Prototypical User Interface): for every bin b of an update's
+ * outputs `bins` (n_bins = W) and field m, counts[b * H + k] = the number of
+ * the bin's cells whose value lies in bucket k of the window [lo, hi]
+ * (H = n_buckets, 1 <= H <= 4096; the bucket of a value is its entry under
+ * the quantiser of [lo, hi] for H entries, as for TF entries; values outside
+ * the window count in the end buckets).  A cell shared by two bins counts in
+ * both.  counts: device uint32[W * H], caller-owned.  Asynchronous (after
+ * the update on `stream`).  Errors: DVL_E_INVALID.
+ * ------------------------------------------------------------------- */
+dvl_status dvl_bin_histograms(const dvl_volume* v, const dvl_bins* bins, int32_t n_bins, int32_t m,
+                              int32_t n_buckets, float lo, float hi, uint32_t* counts, void* stream);
+
+/* ---------------------------------------------------------------------
+ * dvl_rasterize -- RasterizeLines (GPU Implementation section): the volume
+ * lines drawn as polylines or bar charts.  y: device float[n_lines * W],
+ * line l's heights (an update's y output, values in [0, 1]); image: device
+ * uint8[n_lines * n_rows * W], image l row r (row 0 at the bottom) column b
+ * at (l * n_rows + r) * W + b, 1 for a drawn pixel, else 0.  The row of a
+ * height is min(n_rows - 1, floor(y * n_rows)) (fp32).
+ * DVL_RASTER_POLYLINE: column b holds the rows from the row of y[b] to the
+ * row of y[b + 1] (the last column: its own row); DVL_RASTER_BARS: rows 0 to
+ * the row of y[b].  1 <= n_lines <= 16, 1 <= W <= 2^20, 1 <= n_rows <= 16384.
+ * Asynchronous.  Errors: DVL_E_INVALID.
+ * ------------------------------------------------------------------- */
+#define DVL_RASTER_POLYLINE 0
+#define DVL_RASTER_BARS     1
+dvl_status dvl_rasterize(const float* y, int32_t n_lines, int32_t n_bins, int32_t n_rows, int32_t mode,
+                         uint8_t* image, void* stream);
+
+/* ---------------------------------------------------------------------
  * Per-kernel timing of updates (profiling aid).  While enabled, every
  * dvl_update records HIP events on its stream around each of its kernels:
  * phase 0 exact max(V) (VMAX_EXACT only), 1 tile sums of the importance,

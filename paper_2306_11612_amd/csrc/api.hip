@@ -15,6 +15,7 @@
 
 #include "order.hpp"
 #include "update.hpp"
+#include "views.hpp"
 
 namespace dvl {
 
@@ -669,6 +670,8 @@ static BatchDev batch_dev(const Plan& P, char* d, int paths) {
     b.max_req_tf = P.max_req_tf;
     b.max_job_tf = P.max_job_tf;
     b.max_req_job = P.max_req;
+    b.max_tile_steps = 8;
+    for (const JobDev& j : P.jobs) b.max_tile_steps = std::max(b.max_tile_steps, j.tile_steps);
     return b;
 }
 
@@ -888,12 +891,21 @@ struct dvl_graph {
     hipEvent_t ev[kRing] = {};
     bool used[kRing] = {};
     int next = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // one captured graph per set of projection paths (values, cached
+    // entries, stored f): a replay launches only the kernel variants its jobs
+    // use, and the set can change between launches as entry caches appear
+    struct Captured {
+        int paths;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<Captured> captured;
     ~dvl_graph() {
         (void)hipDeviceSynchronize();
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        for (auto& c : captured) {
+            if (c.exec) (void)hipGraphExecDestroy(c.exec);
+            if (c.graph) (void)hipGraphDestroy(c.graph);
+        }
         alloc.put(dev, nullptr);
         for (void* w : ws) alloc.put(w, nullptr);
         for (int r = 0; r < kRing; ++r) {
@@ -1047,8 +1059,8 @@ dvl_status dvl_build_order_ex(int64_t n, const int32_t* x, const int32_t* y, con
         DevBuf fb(A);
         if (dvl_status st = fb.alloc((size_t)v->n_pad * eb, "sorted field")) return st;
         DVL_HIP(hipMemsetAsync((char*)fb.p + (size_t)n * eb, 0, (size_t)(v->n_pad - n) * eb, s));
-        if (dvl_status st = launch_gather(n, v->perm, fields[m], fb.p, eb, s)) return st;
-        if (dvl_status st = launch_range(n, dtype, fb.p, (unsigned int*)rng.p + 4 * m, s)) return st;
+        if (dvl_status st = launch_gather_range(n, v->perm, dtype, fields[m], fb.p, (unsigned int*)rng.p + 4 * m, s))
+            return st;
         v->fields_s[m] = fb.release();
         v->bytes += (size_t)v->n_pad * eb;
     }
@@ -1349,6 +1361,204 @@ dvl_status dvl_export_sorted(const dvl_volume* v, uint8_t* level, void* const* f
     return DVL_OK;
 }
 
+// ------------------------------------------------------------------ bin views, brushing, zoom
+
+static dvl_status check_bins_of(const dvl_volume* v, const dvl_bins* b, int32_t W) {
+    if (dvl_status st = check_volume(v)) return st;
+    if (!b || !b->first_cell || !b->last_cell) return fail(DVL_E_INVALID, "bins is NULL or lacks first/last");
+    if (W < 1 || W > (1 << 20)) return fail(DVL_E_INVALID, "n_bins=%d outside [1, 2^20]", W);
+    return DVL_OK;
+}
+
+dvl_status dvl_select_bins(const dvl_volume* v, const dvl_bins* bins, int32_t W, int32_t b0, int32_t b1,
+                           void* stream, uint32_t* first, uint32_t* last, uint64_t* key_lo, uint64_t* key_hi) {
+    g_err.clear();
+    if (dvl_status st = check_bins_of(v, bins, W)) return st;
+    if (b0 < 0 || b1 < b0 || b1 >= W) return fail(DVL_E_INVALID, "bin range [%d, %d] outside [0, %d)", b0, b1, W);
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t f = 0, l = 0;
+    DVL_HIP(hipMemcpyAsync(&f, bins->first_cell + b0, 4, hipMemcpyDeviceToHost, s));
+    DVL_HIP(hipMemcpyAsync(&l, bins->last_cell + b1, 4, hipMemcpyDeviceToHost, s));
+    DVL_HIP(hipStreamSynchronize(s));
+    if (f > l || (int64_t)l >= v->n) return fail(DVL_E_STATE, "the bins do not hold a cell range of this volume");
+    uint64_t klo = 0, khi = 0;
+    DVL_HIP(hipMemcpyAsync(&klo, v->keys_s + f, 8, hipMemcpyDeviceToHost, s));
+    DVL_HIP(hipMemcpyAsync(&khi, v->keys_s + l, 8, hipMemcpyDeviceToHost, s));
+    DVL_HIP(hipStreamSynchronize(s));
+    if (first) *first = f;
+    if (last) *last = l;
+    if (key_lo) *key_lo = klo;
+    if (key_hi) *key_hi = khi;
+    return DVL_OK;
+}
+
+dvl_status dvl_select_mask(const dvl_volume* v, const uint64_t* ranges, int32_t n_ranges, uint8_t* mask,
+                           void* stream) {
+    g_err.clear();
+    if (dvl_status st = check_volume(v)) return st;
+    if (n_ranges < 1 || n_ranges > kMaxSelectRanges)
+        return fail(DVL_E_INVALID, "n_ranges=%d outside [1, %d]", n_ranges, kMaxSelectRanges);
+    if (!ranges || !mask) return fail(DVL_E_INVALID, "ranges or mask is NULL");
+    for (int i = 0; i < n_ranges; ++i)
+        if (ranges[2 * i] > ranges[2 * i + 1]) return fail(DVL_E_INVALID, "range %d has lo > hi", i);
+    return launch_select_mask(v->n, v->keys_s, v->perm, n_ranges, ranges, mask, (hipStream_t)stream);
+}
+
+dvl_status dvl_bin_histograms(const dvl_volume* v, const dvl_bins* bins, int32_t W, int32_t m, int32_t n_buckets,
+                              float lo, float hi, uint32_t* counts, void* stream) {
+    g_err.clear();
+    if (dvl_status st = check_bins_of(v, bins, W)) return st;
+    if (m < 0 || m >= v->M) return fail(DVL_E_INVALID, "field index %d outside [0, %d)", m, v->M);
+    if (n_buckets < 1 || n_buckets > kMaxTfEntries)
+        return fail(DVL_E_INVALID, "n_buckets=%d outside [1, %d]", n_buckets, kMaxTfEntries);
+    if (!counts) return fail(DVL_E_INVALID, "counts is NULL");
+    if (!isfinite(lo) || !isfinite(hi) || !(lo < hi)) return fail(DVL_E_INVALID, "window [%g, %g] is not finite with lo < hi", lo, hi);
+    float qs, qb;
+    quantiser(n_buckets, lo, hi, &qs, &qb);
+    if (!isfinite(qs) || !isfinite(qb)) return fail(DVL_E_INVALID, "window [%g, %g] is too narrow for fp32", lo, hi);
+    return launch_bin_histograms(v->dtype, v->fields_s[m], W, bins->first_cell, bins->last_cell, n_buckets, qs, qb,
+                                 counts, v->n_cu, (hipStream_t)stream);
+}
+
+dvl_status dvl_rasterize(const float* y, int32_t n_lines, int32_t W, int32_t n_rows, int32_t mode, uint8_t* image,
+                         void* stream) {
+    g_err.clear();
+    if (!y || !image) return fail(DVL_E_INVALID, "y or image is NULL");
+    if (n_lines < 1 || n_lines > kMaxFields) return fail(DVL_E_INVALID, "n_lines=%d outside [1, %d]", n_lines, kMaxFields);
+    if (W < 1 || W > (1 << 20)) return fail(DVL_E_INVALID, "n_bins=%d outside [1, 2^20]", W);
+    if (n_rows < 1 || n_rows > 16384) return fail(DVL_E_INVALID, "n_rows=%d outside [1, 16384]", n_rows);
+    if (mode != DVL_RASTER_POLYLINE && mode != DVL_RASTER_BARS) return fail(DVL_E_INVALID, "raster mode %d", mode);
+    return launch_rasterize(y, W, n_rows, n_lines, mode, image, (hipStream_t)stream);
+}
+
+dvl_status dvl_zoom(const dvl_volume* v, uint32_t first, uint32_t last, const dvl_build_options* opt, void* stream,
+                    dvl_volume** out) {
+    g_err.clear();
+    if (!out) return fail(DVL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (dvl_status st = check_volume(v)) return st;
+    if (first > last || (int64_t)last >= v->n)
+        return fail(DVL_E_INVALID, "cell range [%u, %u] outside [0, %lld)", first, last, (long long)v->n);
+    int tile_steps = kDefaultTileSteps, run_waves = 0, entry_cache = DVL_ENTRY_CACHE_AUTO;
+    Alloc alloc = v->alloc;
+    if (opt) {
+        if (opt->allocator)
+            if (dvl_status st = make_alloc(opt->allocator, alloc)) return st;
+        if (opt->entry_cache < DVL_ENTRY_CACHE_AUTO || opt->entry_cache > DVL_ENTRY_CACHE_NEVER)
+            return fail(DVL_E_INVALID, "entry_cache %d", opt->entry_cache);
+        if (opt->tile_steps != 0 && opt->tile_steps != 8 && opt->tile_steps != 16 && opt->tile_steps != 32)
+            return fail(DVL_E_INVALID, "tile_steps %d (0, 8, 16 or 32)", opt->tile_steps);
+        if (opt->run_waves != 0 && (opt->run_waves < 64 || opt->run_waves > 65536))
+            return fail(DVL_E_INVALID, "run_waves %d outside [64, 65536]", opt->run_waves);
+        entry_cache = opt->entry_cache;
+        if (opt->tile_steps) tile_steps = opt->tile_steps;
+        run_waves = opt->run_waves;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = (int64_t)last - first + 1;
+    const int eb = elem_bytes_of(v->dtype);
+    dvl_volume* z = new (std::nothrow) dvl_volume();
+    if (!z) return fail(DVL_E_NOMEM, "host allocation failed");
+    struct Guard { dvl_volume* v; ~Guard() { if (v) dvl_destroy(v); } } guard{z};
+    z->alloc = alloc;
+    const Alloc& A = z->alloc;
+    z->n = n;
+    z->M = v->M;
+    z->dtype = v->dtype;
+    z->bits = v->bits;
+    z->max_level = v->max_level;
+    z->device = v->device;
+    z->n_cu = v->n_cu;
+    z->tile_steps = tile_steps;
+    z->idx_policy = entry_cache;
+    const int64_t tile_cells = (int64_t)tile_steps * kStepCells;
+    z->n_tiles = (n + tile_cells - 1) / tile_cells;
+    z->n_pad = z->n_tiles * tile_cells;
+    {
+        const int64_t waves = run_waves ? run_waves : (int64_t)z->n_cu * 32;
+        z->tiles_per_run = std::max<int64_t>(1, (z->n_tiles + waves - 1) / waves);
+        z->n_runs = (z->n_tiles + z->tiles_per_run - 1) / z->tiles_per_run;
+    }
+    // the range's keys, an identity permutation (its original order is the range)
+    {
+        DevBuf kb(A), pb(A);
+        if (dvl_status st = kb.alloc((size_t)n * 8, "keys")) return st;
+        if (dvl_status st = pb.alloc((size_t)n * 4, "permutation")) return st;
+        DVL_HIP(hipMemcpyAsync(kb.p, v->keys_s + first, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+        if (dvl_status st = launch_iota(n, (uint32_t*)pb.p, s)) return st;
+        z->keys_s = (uint64_t*)kb.release();
+        z->perm = (uint32_t*)pb.release();
+        z->bytes += (size_t)n * 12;
+    }
+    {
+        DevBuf lv(A);
+        if (dvl_status st = lv.alloc((size_t)z->n_pad, "sorted levels")) return st;
+        DVL_HIP(hipMemsetAsync((char*)lv.p + n, 0, (size_t)(z->n_pad - n), s));
+        DVL_HIP(hipMemcpyAsync(lv.p, v->level_s + first, (size_t)n, hipMemcpyDeviceToDevice, s));
+        z->level_s = (uint8_t*)lv.release();
+        z->bytes += (size_t)z->n_pad;
+        DevBuf lc(A);
+        const int64_t n_steps = z->n_pad / kStepCells;
+        if (dvl_status st = lc.alloc((size_t)n_steps * 4, "level codes")) return st;
+        if (dvl_status st = launch_level_codes(z->level_s, n_steps, (uint32_t*)lc.p, s)) return st;
+        z->lcode_s = (uint32_t*)lc.release();
+        z->bytes += (size_t)n_steps * 4;
+    }
+    DevBuf rng(A);
+    if (dvl_status st = rng.alloc((size_t)kMaxFields * 4 * sizeof(unsigned int), "ranges")) return st;
+    std::vector<unsigned int> rinit(kMaxFields * 4, 0u);
+    for (int m = 0; m < kMaxFields; ++m) rinit[m * 4] = 0xFFFFFFFFu;
+    DVL_HIP(hipMemcpyAsync(rng.p, rinit.data(), rinit.size() * 4, hipMemcpyHostToDevice, s));
+    for (int m = 0; m < z->M; ++m) {
+        DevBuf fb(A);
+        if (dvl_status st = fb.alloc((size_t)z->n_pad * eb, "sorted field")) return st;
+        DVL_HIP(hipMemsetAsync((char*)fb.p + (size_t)n * eb, 0, (size_t)(z->n_pad - n) * eb, s));
+        DVL_HIP(hipMemcpyAsync(fb.p, (const char*)v->fields_s[m] + (size_t)first * eb, (size_t)n * eb,
+                               hipMemcpyDeviceToDevice, s));
+        if (dvl_status st = launch_range(n, z->dtype, fb.p, (unsigned int*)rng.p + 4 * m, s)) return st;
+        z->fields_s[m] = fb.release();
+        z->bytes += (size_t)z->n_pad * eb;
+    }
+    {
+        DevBuf as(A), an(A), ax(A), ss(A), sn(A), sx(A);
+        const size_t mt = (size_t)z->M * z->n_tiles;
+        const size_t ms = mt * z->tile_steps;
+        if (dvl_status st = as.alloc(mt * 8, "tile sums")) return st;
+        if (dvl_status st = an.alloc(mt * 4, "tile minima")) return st;
+        if (dvl_status st = ax.alloc(mt * 4, "tile maxima")) return st;
+        if (dvl_status st = ss.alloc(ms * 8, "step sums")) return st;
+        if (dvl_status st = sn.alloc(ms * 4, "step minima")) return st;
+        if (dvl_status st = sx.alloc(ms * 4, "step maxima")) return st;
+        z->agg_sum = (double*)as.release();
+        z->agg_min = (float*)an.release();
+        z->agg_max = (float*)ax.release();
+        z->step_sum = (double*)ss.release();
+        z->step_min = (float*)sn.release();
+        z->step_max = (float*)sx.release();
+        z->bytes += (mt + ms) * 16;
+        for (int m = 0; m < z->M; ++m)
+            if (dvl_status st = tile_aggregates(z, m, s)) return st;
+    }
+    DVL_HIP(hipMemcpyAsync(rinit.data(), rng.p, rinit.size() * 4, hipMemcpyDeviceToHost, s));
+    DVL_HIP(hipStreamSynchronize(s));
+    for (int m = 0; m < z->M; ++m) {
+        z->dmin[m] = unkey(rinit[m * 4]);
+        z->dmax[m] = unkey(rinit[m * 4 + 1]);
+    }
+    {
+        DevBuf sr(A);
+        if (dvl_status st = sr.alloc(4 * sizeof(unsigned int), "range scratch")) return st;
+        z->scratch_range = (unsigned int*)sr.release();
+        z->bytes += 4 * sizeof(unsigned int);
+    }
+    DVL_HIP(hipEventCreateWithFlags(&z->cache_ready, hipEventDisableTiming));
+    if (dvl_status st = new_executor(A, &z->ex)) return st;
+    if (dvl_status st = z->ex->ensure_ws(0, request_ws_bytes(z, 1))) return st;
+    guard.v = nullptr;
+    *out = z;
+    return DVL_OK;
+}
+
 dvl_status dvl_set_timing(dvl_volume* v, int32_t enable) {
     g_err.clear();
     if (dvl_status st = check_volume(v)) return st;
@@ -1519,22 +1729,44 @@ dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph**
         }
         DVL_HIP(hipEventCreateWithFlags(&g->ev[r], hipEventDisableTiming));
     }
-    // capture the kernels once; the descriptors they read are refreshed before each replay
+    // the kernels are captured at the first launch with each set of paths;
+    // the descriptors they read are refreshed before every replay
+    guard.g = nullptr;
+    *out = g;
+    return DVL_OK;
+}
+
+// The executable graph of this path set, captured on first use.
+static dvl_status graph_exec_for(dvl_graph* g, int paths, hipGraphExec_t* out) {
+    for (auto& c : g->captured)
+        if (c.paths == paths) {
+            *out = c.exec;
+            return DVL_OK;
+        }
+    Plan& P = g->plan;
     hipStream_t cs;
     DVL_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     if (hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) {
         (void)hipStreamDestroy(cs);
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    const dvl_status cst = launch_batch(batch_dev(P, g->dev, kPathValues | kPathEntries | kPathStoredF), P.dtype, P.max_m,
-                                        P.max_req, g->n_cu, cs, kDescriptorLayout, nullptr);
-    const hipError_t ee = hipStreamEndCapture(cs, &g->graph);
+    const dvl_status cst =
+        launch_batch(batch_dev(P, g->dev, paths), P.dtype, P.max_m, P.max_req, g->n_cu, cs, kDescriptorLayout, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);
     (void)hipStreamDestroy(cs);
-    if (cst != DVL_OK) return cst;
+    if (cst != DVL_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cst;
+    }
     if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
-    DVL_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
-    guard.g = nullptr;
-    *out = g;
+    hipGraphExec_t exec = nullptr;
+    if (hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    g->captured.push_back({paths, graph, exec});
+    *out = exec;
     return DVL_OK;
 }
 
@@ -1567,12 +1799,18 @@ dvl_status dvl_graph_launch(dvl_graph* g, void* stream) {
     if (dvl_status st = decide_cache(g->plan, builds)) return st;
     if (dvl_status st = run_cache_builds(builds, s)) return st;
     if (dvl_status st = cache_wait(g->plan, s)) return st;
+    int paths = 0;
+    for (const JobDev& j : g->plan.jobs) paths |= j.idx[0] ? kPathEntries : kPathValues;
+    for (const ReqDev& d : g->plan.rdev)
+        if (d.ws.fstore) paths |= kPathStoredF;
+    hipGraphExec_t exec = nullptr;
+    if (dvl_status st = graph_exec_for(g, paths, &exec)) return st;
     if (dvl_status st = fill_block(g->plan, g->host[r], g->dev)) return st;
     g->next = (r + 1) % kRing;
     DVL_HIP(hipMemcpyAsync(g->dev, g->host[r], g->plan.block_bytes, hipMemcpyHostToDevice, s));
     DVL_HIP(hipEventRecord(g->ev[r], s));
     g->used[r] = true;
-    DVL_HIP(hipGraphLaunch(g->exec, s));
+    DVL_HIP(hipGraphLaunch(exec, s));
     return cache_mark_readers(g->plan, s);
 }
 

@@ -255,8 +255,10 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(int64_t n, const uint6
     __shared__ uint32_t tbase[kRadix];                      // tile-local start of each digit
     __shared__ uint32_t gbase[kRadix];                      // global start of each digit for this tile
     __shared__ uint32_t wsum[kSortThreads / kWave];
-    __shared__ uint64_t skey[kSortTile];
-    __shared__ uint32_t sval[kSortTile];
+    // the tile in digit order: keys first, then (in the same space) values,
+    // so that four workgroups fit a compute unit's LDS
+    __shared__ uint64_t stage[kSortTile];
+    uint32_t* sval = reinterpret_cast<uint32_t*>(stage);
 
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -319,27 +321,47 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(int64_t n, const uint6
     }
     __syncthreads();
 
+    // positions in digit order, kept for the value pass
+    uint32_t pos[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int li = w * (kWave * kSortItems) + r * kWave + lane;
+        pos[r] = 0xFFFFFFFFu;
         if (li < n_here) {
             const uint32_t d = (uint32_t)(key[r] >> shift) & 0xFFu;
-            const uint32_t pos = tbase[d] + whist[w][d] + rank[r];
-            if (pos < (uint32_t)kSortTile) {
-                skey[pos] = key[r];
-                sval[pos] = val[r];
+            const uint32_t p = tbase[d] + whist[w][d] + rank[r];
+            if (p < (uint32_t)kSortTile) {
+                pos[r] = p;
+                stage[p] = key[r];
             }
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n_here; i += kSortThreads) {
-        const uint64_t k = skey[i];
-        const uint32_t d = (uint32_t)(k >> shift) & 0xFFu;
-        const int64_t g = (int64_t)gbase[d] + (i - (int64_t)tbase[d]);
-        if (g >= 0 && g < n) {
-            kout[g] = k;
-            vout[g] = sval[i];
+    // keys out (contiguous runs per digit); remember each slot's destination
+    uint32_t dest[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int i = r * kSortThreads + threadIdx.x;
+        dest[r] = 0xFFFFFFFFu;
+        if (i < n_here) {
+            const uint64_t k = stage[i];
+            const uint32_t d = (uint32_t)(k >> shift) & 0xFFu;
+            const int64_t g = (int64_t)gbase[d] + (i - (int64_t)tbase[d]);
+            if (g >= 0 && g < n) {
+                kout[g] = k;
+                dest[r] = (uint32_t)g;
+            }
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+        if (pos[r] != 0xFFFFFFFFu) sval[pos[r]] = val[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int i = r * kSortThreads + threadIdx.x;
+        if (i < n_here && dest[r] != 0xFFFFFFFFu) vout[dest[r]] = sval[i];
     }
 }
 
@@ -420,6 +442,40 @@ __global__ __launch_bounds__(256) void k_range(int64_t n, const typename S::raw*
     }
 }
 
+// gather of one field into sorted order fused with its data range (the
+// order-preserving uint map of k_range; out[0] min, out[1] max, out[2] NaN)
+template <typename S>
+__global__ __launch_bounds__(256) void k_gather_range(int64_t n, const uint32_t* __restrict__ perm,
+                                                      const typename S::raw* __restrict__ src,
+                                                      typename S::raw* __restrict__ dst,
+                                                      unsigned int* __restrict__ out) {
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u, nan = 0u;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t p = perm[i];
+        if (p >= (uint64_t)n) continue;
+        const typename S::raw r = src[p];
+        dst[i] = r;
+        const float f = to_f32(S{}, r);
+        if (f != f) { nan = 1u; continue; }
+        uint32_t u = __float_as_uint(f);
+        u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+        lo = min(lo, u);
+        hi = max(hi, u);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const int l = lane_id() ^ o;
+        lo = min(lo, (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)lo));
+        hi = max(hi, (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)hi));
+        nan |= (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)nan);
+    }
+    if (lane_id() == 0) {
+        atomicMin(&out[0], lo);
+        atomicMax(&out[1], hi);
+        if (nan) atomicOr(&out[2], 1u);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_scatter_back(int64_t n, const uint32_t* __restrict__ perm,
                                                       const T* __restrict__ sorted, T* __restrict__ orig) {
@@ -477,6 +533,21 @@ dvl_status launch_scatter_back(int64_t n, const uint32_t* perm, const void* sort
                            (const uint64_t*)sorted, (uint64_t*)orig);
     else
         return DVL_E_INVALID;
+    DVL_HIP(hipGetLastError());
+    return DVL_OK;
+}
+
+dvl_status launch_gather_range(int64_t n, const uint32_t* perm, int dtype, const void* src, void* dst,
+                               unsigned int* out, hipStream_t s) {
+    if (dtype == DVL_F32)
+        hipLaunchKernelGGL(k_gather_range<F32>, dim3(grid_for(n)), dim3(256), 0, s, n, perm, (const float*)src,
+                           (float*)dst, out);
+    else if (dtype == DVL_F16)
+        hipLaunchKernelGGL(k_gather_range<F16>, dim3(grid_for(n)), dim3(256), 0, s, n, perm, (const uint16_t*)src,
+                           (uint16_t*)dst, out);
+    else
+        hipLaunchKernelGGL(k_gather_range<BF16>, dim3(grid_for(n)), dim3(256), 0, s, n, perm, (const uint16_t*)src,
+                           (uint16_t*)dst, out);
     DVL_HIP(hipGetLastError());
     return DVL_OK;
 }

@@ -23,5 +23,8 @@ dvl_status launch_scatter_back(int64_t n, const uint32_t* perm, const void* sort
                                int elem_bytes, hipStream_t s);
 // out[0] = min, out[1] = max as order-preserving uint keys, out[2] = NaN seen
 dvl_status launch_range(int64_t n, int dtype, const void* v, unsigned int* out, hipStream_t s);
+// dst[i] = src[perm[i]] for a field of storage `dtype`, with the range of the values as launch_range
+dvl_status launch_gather_range(int64_t n, const uint32_t* perm, int dtype, const void* src, void* dst,
+                               unsigned int* out, hipStream_t s);
 
 }  // namespace dvl

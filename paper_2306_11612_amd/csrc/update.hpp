@@ -117,6 +117,7 @@ struct BatchDev {
     int max_req_tf;           // largest request table block (floats): LDS of the projection
     int max_job_tf;           // largest job table block (floats): LDS of the importance pass
     int max_req_job;          // most requests in one job
+    int max_tile_steps;       // largest tile (256-cell steps) of the batch's volumes
 };
 
 // The descriptor layout a translation unit was compiled with.  The host

@@ -248,7 +248,10 @@ __device__ __forceinline__ void table_offsets(const ReqDev& q, int M, int (&off)
 // steps and are padded, so the loads of a group stay inside the volume's
 // buffers).
 template <typename D> struct Group { static constexpr int n = 1; };
-template <int MT> struct Group<StepIdx<MT>> { static constexpr int n = 4; };
+#ifndef DVL_ENTRY_GROUP
+#define DVL_ENTRY_GROUP 4
+#endif
+template <int MT> struct Group<StepIdx<MT>> { static constexpr int n = DVL_ENTRY_GROUP; };
 template <int MT> struct Group<StepData<MT, F16>> { static constexpr int n = 2; };
 template <int MT> struct Group<StepData<MT, BF16>> { static constexpr int n = 2; };
 
@@ -583,7 +586,12 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
 // A workgroup takes 4 consecutive runs of one job; wave r of the job owns the
 // tiles [r k, (r + 1) k).
 template <int MT, typename S, int KR, int IDX>
-__global__ __launch_bounds__(kUpdThreads) void k_tile_sums(BatchDev b) {
+#ifdef DVL_K1_WAVES_PER_EU
+#define DVL_K1_OCCUPANCY __attribute__((amdgpu_waves_per_eu(DVL_K1_WAVES_PER_EU)))
+#else
+#define DVL_K1_OCCUPANCY
+#endif
+__global__ __launch_bounds__(kUpdThreads) DVL_K1_OCCUPANCY void k_tile_sums(BatchDev b) {
     extern __shared__ float tf_lds[];
     const int wv = uni((int)(thread_x() / kWave));
     int loaded = -1;
@@ -665,7 +673,7 @@ __device__ __forceinline__ void close_bin(const ReqDev& q, int64_t T, int dest, 
 
 // ------------------------------------------------------------------ K3
 
-constexpr int kBinThreads = 64;   // one wave per workgroup: each unit is one (request, tile)
+constexpr int kBinThreads = 256;  // one workgroup per queued (request, tile)
 
 // Pixel interval [X0, X1] of tile t of request q, and its first and last bin.
 struct TileSpan {
@@ -711,27 +719,51 @@ __device__ __forceinline__ float rescan_v(const StepIdx<MT>& d, int k, int M, co
     return amax - amin;
 }
 
-// One queued tile of request q: f of every cell again (from values or cached
-// entries, bit for bit as in K1), monotone in-tile prefix, pixel interval and
-// bins of every cell; each bin's cell range is closed as soon as it is known
-// and its statistics taken from the values at its ends and the per-step
-// statistics in between.
+// The in-step prefix of one 256-cell step, per lane (4 cells): the wave's
+// exclusive prefix before the lane (Bex), the lane's own partial sums p1..p3
+// and the inclusive prefix B through the lane (running maximum: never
+// decreasing).  Staged in LDS by the first phase of the rescan.
+struct StepPrefix {
+    f32x4 ex_p;   // Bex, p1, p2, p3
+    float B;
+};
+
+// LDS of the staged prefixes of one tile: [steps][64] (Bex, p1, p2, p3) and
+// [steps][64] B, at most kMaxTileSteps steps
+struct Stage {
+    f32x4* ex_p;
+    float* B;
+    __device__ void put(int i, const StepPrefix& p) {
+        ex_p[i] = p.ex_p;
+        B[i] = p.B;
+    }
+    __device__ StepPrefix get(int i) const {
+        StepPrefix p;
+        p.ex_p = ex_p[i];
+        p.B = B[i];
+        return p;
+    }
+};
+
+constexpr int kBinWaves = kBinThreads / kWave;
+constexpr int kMaxTileSteps = 32;
+constexpr size_t kStageBytesPerStep = (size_t)kWave * (sizeof(f32x4) + sizeof(float));
+
+// Phase 1 of the rescan, for the steps s = w, w + kBinWaves, ... of tile t
+// taken by wave w: f of every cell again (from values, cached entries or the
+// stored f, bit for bit as in K1; 1 when the total importance is 0) and the
+// step's monotone prefix, into LDS.  Loads run one step ahead.
 template <int MT, typename S, typename D>
-__device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, int64_t t, const float* tf_lds) {
+__device__ __forceinline__ void rescan_stage(const ReqDev& q, const JobDev& j, int64_t t, const float* tf_lds,
+                                             Stage stage) {
     const int lane = lane_id();
+    const int w = uni((int)(thread_x() / kWave));
     const int M = uni(fields_of<MT>(j.M));
-    const int64_t T = uni(j.n_tiles);
     const int64_t n = uni(j.n);
     const bool degenerate = uni((int)(gload<double>(q.ws.scal, 1) != 0.0)) != 0;
-    const TileSpan sp = tile_span(q, j, t);
-    const float scale_f = uni(sp.scale_f), X0 = uni(sp.X0), X1 = uni(sp.X1);
-    const int W1 = uni(q.W) - 1;
     const int tile_steps = uni(j.tile_steps);
-    const int64_t tile_cells = (int64_t)tile_steps * kStepCells;
-    const int64_t tbase = t * tile_cells;
-    const int64_t tend = min(tbase + tile_cells, n);
-    const uint32_t last_valid = (uint32_t)(tend - 1);
-    const int nsteps = (int)((tend - tbase + kStepCells - 1) / kStepCells);
+    const int64_t tbase = t * (int64_t)tile_steps * kStepCells;
+    const int nsteps = (int)((min(tbase + (int64_t)tile_steps * kStepCells, n) - tbase + kStepCells - 1) / kStepCells);
     RunView<MT> view;
     if constexpr (std::is_same<D, StepF<MT>>::value) {
         view = run_view<MT, StepData<MT, S>>(j, M, tbase);
@@ -742,50 +774,68 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
     const ImpCtx c = make_ctx(q);
     int off[MT];
     table_offsets<MT>(q, M, off);
+    if (w >= nsteps) return;
+    D cur, nxt;
+    cur.load(view, M, w, gload<uint32_t>(view.lcode, w));
+    for (int s = w; s < nsteps; s += kBinWaves) {
+        const int sn = min(s + kBinWaves, nsteps - 1);
+        nxt.load(view, M, sn, gload<uint32_t>(view.lcode, sn));
+        const int64_t quad = ((tbase + (int64_t)s * kStepCells) >> 2) + lane;
+        float f[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float fk = 1.0f;
+            if constexpr (std::is_same<D, StepF<MT>>::value) {
+                if (!degenerate) fk = k == 0 ? cur.fv.x : (k == 1 ? cur.fv.y : (k == 2 ? cur.fv.z : cur.fv.w));
+            } else {
+                if (!degenerate) fk = importance_from_v(rescan_v<MT>(cur, k, M, tf_lds, q, off), cur.lv.get(k), c);
+            }
+            f[k] = ((quad << 2) + k < n) ? fk : 0.0f;
+        }
+        // monotone in-tile prefix: lane-serial over 4 cells, wave sum scan,
+        // running max to undo rounding steps back
+        const float p1 = f[0], p2 = p1 + f[1], p3 = p2 + f[2], tl = p3 + f[3];
+        const float B = wave_incl_max(wave_incl_sum(tl));
+        StepPrefix sp;
+        sp.ex_p.x = shfl_up1(B, 0.0f);
+        sp.ex_p.y = p1;
+        sp.ex_p.z = p2;
+        sp.ex_p.w = p3;
+        sp.B = B;
+        stage.put(s * kWave + lane, sp);
+        cur = nxt;
+    }
+}
+
+// Phase 2, by one wave: the cells' pixel intervals and bins from the staged
+// prefixes, step after step (the running base of a step is the fp32 sum of
+// the earlier steps' totals, in order).  Each bin's cell range is closed as
+// soon as it is known: bins inside the tile are written as outputs, the
+// tile's first and last bin as its head and tail records.
+__device__ __forceinline__ void rescan_walk(const ReqDev& q, const JobDev& j, int64_t t, const Stage stage) {
+    const int lane = lane_id();
+    const int64_t T = uni(j.n_tiles);
+    const int64_t n = uni(j.n);
+    const TileSpan sp = tile_span(q, j, t);
+    const float scale_f = uni(sp.scale_f), X0 = uni(sp.X0), X1 = uni(sp.X1);
+    const int W1 = uni(q.W) - 1;
+    const int tile_steps = uni(j.tile_steps);
+    const int64_t tile_cells = (int64_t)tile_steps * kStepCells;
+    const int64_t tbase = t * tile_cells;
+    const int64_t tend = min(tbase + tile_cells, n);
+    const uint32_t last_valid = (uint32_t)(tend - 1);
+    const int nsteps = (int)((tend - tbase + kStepCells - 1) / kStepCells);
 
     float run = 0.0f;
     bool o_valid = false;
     int O = -1, Bh = -1;
     uint32_t O_first = 0;
 
-    D cur, nx1;
-    // level codes through vector loads issued two steps before the loads
-    // that use them (waited for in order, ahead of the prefetched steps)
-    const uint32_t code0 = gload<uint32_t>(view.lcode, 0);
-    const uint32_t code1 = gload<uint32_t>(view.lcode, min(1, nsteps - 1));
-    uint32_t code2 = gload<uint32_t>(view.lcode, min(2, nsteps - 1));
-    uint32_t code3 = gload<uint32_t>(view.lcode, min(3, nsteps - 1));
-    cur.load(view, M, 0, code0);
-    nx1.load(view, M, min(1, nsteps - 1), code1);
     for (int s = 0; s < nsteps; ++s) {
         const int64_t c0 = tbase + (int64_t)s * kStepCells;
         const int64_t quad = (c0 >> 2) + lane;
-        const uint32_t code4 = gload<uint32_t>(view.lcode, min(s + 4, nsteps - 1));
-        D nxt;
-        nxt.load(view, M, min(s + 2, nsteps - 1), code2);
-
-        float f[4];
-        uint32_t g[4];
-        bool valid[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            g[k] = (uint32_t)((quad << 2) + k);
-            valid[k] = (int64_t)g[k] < n;
-            float fk = 1.0f;
-            if constexpr (std::is_same<D, StepF<MT>>::value) {
-                if (!degenerate) fk = k == 0 ? cur.fv.x : (k == 1 ? cur.fv.y : (k == 2 ? cur.fv.z : cur.fv.w));
-            } else {
-                if (!degenerate)
-                    fk = importance_from_v(rescan_v<MT>(cur, k, M, tf_lds, q, off), cur.lv.get(k), c);
-            }
-            f[k] = valid[k] ? fk : 0.0f;
-        }
-
-        // monotone in-tile prefix: lane-serial over 4 cells, wave sum scan,
-        // running max to undo rounding steps back, min-clamp inside the lane
-        const float p1 = f[0], p2 = p1 + f[1], p3 = p2 + f[2], tl = p3 + f[3];
-        const float B = wave_incl_max(wave_incl_sum(tl));
-        const float Bex = shfl_up1(B, 0.0f);
+        const StepPrefix pr = stage.get(s * kWave + lane);
+        const float Bex = pr.ex_p.x, p1 = pr.ex_p.y, p2 = pr.ex_p.z, p3 = pr.ex_p.w, B = pr.B;
         const float stot = readlane(B, kWave - 1);
         const bool full = c0 + kStepCells <= n;
 
@@ -813,13 +863,16 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
                 O_first = (uint32_t)c0;
             }
             run = run + stot;
-            cur = nx1;
-            nx1 = nxt;
-            code2 = code3;
-            code3 = code4;
             continue;
         }
 
+        uint32_t g[4];
+        bool valid[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            g[k] = (uint32_t)((quad << 2) + k);
+            valid[k] = (int64_t)g[k] < n;
+        }
         float xs[5];
         xs[0] = fminf(fmaf(run + fminf(Bex, B), scale_f, X0), X1);
         xs[1] = fminf(fmaf(run + fminf(Bex + p1, B), scale_f, X0), X1);
@@ -888,10 +941,6 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
             b = wave_min_i32(nk);
             if (b == INT_MAX) break;   // cannot happen: key_last is above
         }
-        cur = nx1;
-        nx1 = nxt;
-        code2 = code3;
-        code3 = code4;
     }
 
     // tile end: the open bin is the tile's last bin
@@ -904,16 +953,21 @@ __device__ __forceinline__ void rescan_tile(const ReqDev& q, const JobDev& j, in
     }
 }
 
-// K3b: the queued tiles, one wave each.  IDX: this instance serves the
-// requests whose projection reads values (0), cached entries (1) or the f the
-// importance pass stored (2); each skips the others' tiles.
+// K3b: the queued tiles, one workgroup each.  Its waves stage the prefixes
+// of the tile's steps in LDS together (phase 1; the loads of four waves in
+// flight instead of one), then the first wave walks the bins (phase 2).
+// IDX: this instance serves the requests whose projection reads values (0),
+// cached entries (1) or the f the importance pass stored (2); each skips the
+// others' tiles.  LDS: the request's tables, then the staged prefixes.
 template <int MT, typename S, int IDX>
 __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
     extern __shared__ float tf_lds[];
-    const int lane = lane_id();
     int loaded = -1;
     const int64_t n_queued = gload<uint32_t>(bd.rescan_count, IDX);
     const uint64_t* queue = bd.rescan_queue + IDX * bd.k3_units;
+    Stage stage;
+    stage.ex_p = reinterpret_cast<f32x4*>(tf_lds + ((bd.max_req_tf + 3) & ~3));
+    stage.B = reinterpret_cast<float*>(stage.ex_p + (size_t)bd.max_tile_steps * kWave);
 
     for (int64_t i = block_x(); i < n_queued; i += grid_dim_x()) {
         const int64_t u = uni((int64_t)gload<uint64_t>(queue, i));
@@ -923,19 +977,19 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
         const int64_t t = u - uni(q.k3_unit0);
         // the tile is rescanned: this request's tables in LDS
         if (qi != loaded) {
-            __builtin_amdgcn_wave_barrier();
-            for (int i = lane; i < q.tf_total; i += kWave) tf_lds[i] = gload<float>(q.tf, i);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int k = thread_x(); k < q.tf_total; k += kBinThreads) tf_lds[k] = gload<float>(q.tf, k);
             loaded = qi;
         }
+        __syncthreads();
         if constexpr (IDX == 2)
-            rescan_tile<MT, S, StepF<MT>>(q, j, t, tf_lds);
+            rescan_stage<MT, S, StepF<MT>>(q, j, t, tf_lds, stage);
         else if constexpr (IDX == 1)
-            rescan_tile<MT, S, StepIdx<MT>>(q, j, t, tf_lds);
+            rescan_stage<MT, S, StepIdx<MT>>(q, j, t, tf_lds, stage);
         else
-            rescan_tile<MT, S, StepData<MT, S>>(q, j, t, tf_lds);
+            rescan_stage<MT, S, StepData<MT, S>>(q, j, t, tf_lds, stage);
+        __syncthreads();
+        if (thread_x() < kWave) rescan_walk(q, j, t, stage);
+        __syncthreads();
     }
 }
 
@@ -1176,7 +1230,7 @@ static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEv
     if (dvl_status st = launch_carry(b, s)) return st;
     if (dvl_status st = mark(3)) return st;
     if (dvl_status st = launch_classify(b, s)) return st;
-    const size_t lds3 = (size_t)b.max_req_tf * sizeof(float);
+    const size_t lds3 = (size_t)((b.max_req_tf + 3) & ~3) * sizeof(float) + (size_t)b.max_tile_steps * kStageBytesPerStep;
     const unsigned g3 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.k3_units, (int64_t)n_cu * 16));
     if (b.paths & kPathValues) {
         hipLaunchKernelGGL((k_bin<MT, S, 0>), dim3(g3), dim3(kBinThreads), lds3, s, b);

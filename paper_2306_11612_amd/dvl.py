@@ -160,6 +160,11 @@ def lib():
         "dvl_graph_launch": (i32, [vp, vp]),
         "dvl_graph_destroy": (None, [vp]),
         "dvl_last_error": (C.c_char_p, []),
+        "dvl_select_bins": (i32, [vp, C.POINTER(dvl_bins), i32, i32, i32, vp, vp, vp, vp, vp]),
+        "dvl_select_mask": (i32, [vp, vp, i32, vp, vp]),
+        "dvl_bin_histograms": (i32, [vp, C.POINTER(dvl_bins), i32, i32, i32, f32, f32, vp, vp]),
+        "dvl_rasterize": (i32, [vp, i32, i32, i32, i32, vp, vp]),
+        "dvl_zoom": (i32, [vp, C.c_uint32, C.c_uint32, C.POINTER(dvl_build_options), vp, C.POINTER(vp)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -368,6 +373,44 @@ class Volume:
                                        _stream_ptr(stream)), "dvl_export_sorted")
         return level, fields
 
+    # -------------------------------------------------------- brushing, zoom, views
+
+    def select_bins(self, bins: Bins, b0: int, b1: int, stream=None):
+        """dvl_select_bins: (first, last, key_lo, key_hi) of the cells of bins b0..b1."""
+        f, l = C.c_uint32(), C.c_uint32()
+        klo, khi = C.c_uint64(), C.c_uint64()
+        b = bins.struct()
+        _check(lib().dvl_select_bins(self.handle, C.byref(b), bins.n_bins, int(b0), int(b1), _stream_ptr(stream),
+                                     C.byref(f), C.byref(l), C.byref(klo), C.byref(khi)), "dvl_select_bins")
+        return f.value, l.value, klo.value, khi.value
+
+    def select_mask(self, ranges, stream=None) -> torch.Tensor:
+        """dvl_select_mask: uint8 [n] (original order), 1 where the cell's key is
+        in one of the closed ranges [(lo, hi), ...]."""
+        r = np.ascontiguousarray(np.asarray(ranges, dtype=np.uint64).reshape(-1, 2))
+        mask = torch.empty(self.n, dtype=torch.uint8, device="cuda")
+        _check(lib().dvl_select_mask(self.handle, r.ctypes.data_as(C.c_void_p), r.shape[0], _ptr(mask),
+                                     _stream_ptr(stream)), "dvl_select_mask")
+        return mask
+
+    def bin_histograms(self, bins: Bins, m: int, n_buckets: int, lo: float, hi: float, stream=None) -> torch.Tensor:
+        """dvl_bin_histograms: int32 view of the uint32 counts [W, n_buckets]."""
+        counts = torch.empty(bins.n_bins, int(n_buckets), dtype=torch.int32, device="cuda")
+        b = bins.struct()
+        _check(lib().dvl_bin_histograms(self.handle, C.byref(b), bins.n_bins, int(m), int(n_buckets), float(lo),
+                                        float(hi), _ptr(counts), _stream_ptr(stream)), "dvl_bin_histograms")
+        return counts
+
+    def zoom(self, first: int, last: int, stream=None, tile_steps: int = 0, run_waves: int = 0,
+             entry_cache: int = ENTRY_CACHE_AUTO, allocator: Allocator | None = None) -> "Volume":
+        """dvl_zoom: a new volume of the sorted cells first..last."""
+        opt = dvl_build_options(int(tile_steps), int(run_waves), int(entry_cache),
+                                C.pointer(allocator.struct) if allocator is not None else None)
+        out = C.c_void_p()
+        _check(lib().dvl_zoom(self.handle, int(first), int(last), C.byref(opt), _stream_ptr(stream), C.byref(out)),
+               "dvl_zoom")
+        return Volume(out, allocator if allocator is not None else self.allocator)
+
     def set_entry_cache(self, policy: int):
         """dvl_set_entry_cache: ENTRY_CACHE_AUTO / ALWAYS / NEVER (NEVER frees it)."""
         _check(lib().dvl_set_entry_cache(self.handle, int(policy)), "dvl_set_entry_cache")
@@ -405,6 +448,21 @@ class Volume:
             self.close()
         except Exception:
             pass
+
+
+RASTER_POLYLINE, RASTER_BARS = 0, 1
+
+
+def rasterize(y: torch.Tensor, n_rows: int, mode: int = RASTER_POLYLINE, stream=None) -> torch.Tensor:
+    """dvl_rasterize: uint8 images [L, n_rows, W] of the lines y [L, W] (device float32)."""
+    y = _dev(y, torch.float32)
+    if y.dim() == 1:
+        y = y[None]
+    L, W = y.shape
+    img = torch.empty(L, int(n_rows), W, dtype=torch.uint8, device=y.device)
+    _check(lib().dvl_rasterize(_ptr(y), L, W, int(n_rows), int(mode), _ptr(img), _stream_ptr(stream)),
+           "dvl_rasterize")
+    return img
 
 
 def update_workspace_bytes(n_cells: int, n_fields: int, n_bins: int) -> int:
