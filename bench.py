@@ -204,9 +204,10 @@ def bench_batch32(args, dt):
 
     g = dvl.Graph(reqs)
 
+    alt = [[tfs[i][s] for i in range(n_vol)] for s in range(2)]
+
     def graph(k):
-        for i in range(n_vol):
-            g.set_tf(i, tfs[i][k & 1])
+        g.set_tf_all(alt[k & 1])
         g.launch()
     ms_graph = timed(graph, "captured graph")
     cached = all(V.entry_cache_info() is not None for V in vols)

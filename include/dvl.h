@@ -329,6 +329,11 @@ typedef struct dvl_graph dvl_graph;
 dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph** out);
 dvl_status dvl_graph_set_tf(dvl_graph* g, int32_t req, const float* alpha, const float* lo,
                             const float* hi);
+/* every request's tables at once: host arrays of n_reqs pointers (lo, hi may
+ * be NULL, or hold NULL entries: the data ranges); the first failing request
+ * is reported and the later ones are left as they were */
+dvl_status dvl_graph_set_tf_all(dvl_graph* g, const float* const* alpha, const float* const* lo,
+                                const float* const* hi);
 dvl_status dvl_graph_launch(dvl_graph* g, void* stream);
 void dvl_graph_destroy(dvl_graph* g);
 

@@ -1789,6 +1789,20 @@ dvl_status dvl_graph_set_tf(dvl_graph* g, int32_t req, const float* alpha, const
     return DVL_OK;
 }
 
+dvl_status dvl_graph_set_tf_all(dvl_graph* g, const float* const* alpha, const float* const* lo,
+                                const float* const* hi) {
+    g_err.clear();
+    if (!g) return fail(DVL_E_INVALID, "graph is NULL");
+    if (!alpha) return fail(DVL_E_INVALID, "alpha is NULL");
+    const int n = (int)g->plan.where.size();
+    for (int i = 0; i < n; ++i)
+        if (dvl_status st = dvl_graph_set_tf(g, i, alpha[i], lo ? lo[i] : nullptr, hi ? hi[i] : nullptr)) {
+            const std::string msg = g_err;
+            return fail(st, "request %d: %s", i, msg.c_str());
+        }
+    return DVL_OK;
+}
+
 dvl_status dvl_graph_launch(dvl_graph* g, void* stream) {
     g_err.clear();
     if (!g) return fail(DVL_E_INVALID, "graph is NULL");

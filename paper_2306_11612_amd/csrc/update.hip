@@ -217,43 +217,73 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(BatchDev b) {
 
 // K3a.  A tile whose pixel interval lies inside one bin puts every cell in
 // that bin: its head record is the whole tile and no cell is read (the
-// projection is hierarchical over tiles).  Other tiles are queued for K3b,
-// one wave-aggregated atomic per wave.
-__global__ __launch_bounds__(256) void k_classify(BatchDev bd) {
-    const int64_t u = (int64_t)block_x() * 256 + thread_x();
-    bool need = false;
-    int path = 0;
-    if (u < bd.k3_units) {
-        const ReqDev& q = bd.reqs[find_req_k3(bd, u)];
-        const JobDev& j = bd.jobs[q.job];
-        path = q.ws.fstore ? 2 : (j.idx[0] ? 1 : 0);
-        const int64_t t = u - q.k3_unit0;
-        const TileSpan sp = tile_span(q, j, t);
-        if (sp.b0 == sp.b1) {
-            const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
-            const int64_t tbase = t * tile_cells;
-            gstore<uint32_t>(q.ws.rec_first, t, (uint32_t)tbase);
-            gstore<uint32_t>(q.ws.rec_last, t, (uint32_t)(min(tbase + tile_cells, j.n) - 1));
-            gstore<int32_t>(q.ws.head_bin, t, sp.b0);
-            gstore<int32_t>(q.ws.tail_bin, t, sp.b0);
-        } else {
-            need = true;
+// projection is hierarchical over tiles).  Other tiles are queued for K3b.
+// Each thread classifies kClassifyItems tiles; the workgroup appends its
+// queued tiles with one atomic per projection path (a single counter
+// contended by every wave was the cost of this pass).
+constexpr int kClassifyItems = 4;
+constexpr int kClassifyThreads = 256;
+
+__global__ __launch_bounds__(kClassifyThreads) void k_classify(BatchDev bd) {
+    __shared__ uint32_t wcount[3][kClassifyThreads / kWave];
+    __shared__ uint32_t wbase[3];
+    const int lane = lane_id(), w = thread_x() / kWave;
+    const int64_t u0 = (int64_t)block_x() * kClassifyThreads * kClassifyItems;
+    bool need[kClassifyItems];
+    int path[kClassifyItems];
+#pragma unroll
+    for (int r = 0; r < kClassifyItems; ++r) {
+        const int64_t u = u0 + (int64_t)r * kClassifyThreads + thread_x();
+        need[r] = false;
+        path[r] = 0;
+        if (u < bd.k3_units) {
+            const ReqDev& q = bd.reqs[find_req_k3(bd, u)];
+            const JobDev& j = bd.jobs[q.job];
+            path[r] = q.ws.fstore ? 2 : (j.idx[0] ? 1 : 0);
+            const int64_t t = u - q.k3_unit0;
+            const TileSpan sp = tile_span(q, j, t);
+            if (sp.b0 == sp.b1) {
+                const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
+                const int64_t tbase = t * tile_cells;
+                gstore<uint32_t>(q.ws.rec_first, t, (uint32_t)tbase);
+                gstore<uint32_t>(q.ws.rec_last, t, (uint32_t)(min(tbase + tile_cells, j.n) - 1));
+                gstore<int32_t>(q.ws.head_bin, t, sp.b0);
+                gstore<int32_t>(q.ws.tail_bin, t, sp.b0);
+            } else {
+                need[r] = true;
+            }
         }
     }
-    // one queue per projection path (values, cached entries, stored f)
+    // per path: the wave's queued tiles, then one atomic for the workgroup
+    uint32_t mine_before[3][kClassifyItems];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-        const bool mine = need && path == p;
-        const uint64_t mask = __ballot(mine);
-        if (mask) {
-            const int leader = __ffsll((unsigned long long)mask) - 1;
-            uint32_t base = 0;
-            if (lane_id() == leader) base = atomicAdd(bd.rescan_count + p, (uint32_t)__popcll(mask));
-            base = readlane(base, leader);
-            if (mine)
-                gstore<uint64_t>(bd.rescan_queue, p * bd.k3_units + base + (uint32_t)__popcll(mask & lanemask_lt()),
-                                 (uint64_t)u);
+        uint32_t c = 0;
+#pragma unroll
+        for (int r = 0; r < kClassifyItems; ++r) {
+            const uint64_t mask = __ballot(need[r] && path[r] == p);
+            mine_before[p][r] = c + (uint32_t)__popcll(mask & lanemask_lt());
+            c += (uint32_t)__popcll(mask);
         }
+        if (lane == 0) wcount[p][w] = c;
+    }
+    __syncthreads();
+    if (thread_x() < 3) {
+        const int p = thread_x();
+        uint32_t tot = 0;
+        for (int k = 0; k < kClassifyThreads / kWave; ++k) tot += wcount[p][k];
+        wbase[p] = tot ? atomicAdd(bd.rescan_count + p, tot) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        uint32_t base = wbase[p];
+        for (int k = 0; k < w; ++k) base += wcount[p][k];
+#pragma unroll
+        for (int r = 0; r < kClassifyItems; ++r)
+            if (need[r] && path[r] == p)
+                gstore<uint64_t>(bd.rescan_queue, p * bd.k3_units + base + mine_before[p][r],
+                                 (uint64_t)(u0 + (int64_t)r * kClassifyThreads + thread_x()));
     }
 }
 
@@ -412,8 +442,9 @@ dvl_status launch_carry(const BatchDev& b, hipStream_t s) {
 }
 
 dvl_status launch_classify(const BatchDev& b, hipStream_t s) {
-    const unsigned g = (unsigned)std::max<int64_t>(1, (b.k3_units + 255) / 256);
-    hipLaunchKernelGGL(k_classify, dim3(g), dim3(256), 0, s, b);
+    const int64_t per_block = (int64_t)kClassifyThreads * kClassifyItems;
+    const unsigned g = (unsigned)std::max<int64_t>(1, (b.k3_units + per_block - 1) / per_block);
+    hipLaunchKernelGGL(k_classify, dim3(g), dim3(kClassifyThreads), 0, s, b);
     DVL_HIP(hipGetLastError());
     return DVL_OK;
 }

@@ -722,32 +722,37 @@ __device__ __forceinline__ float rescan_v(const StepIdx<MT>& d, int k, int M, co
 // The in-step prefix of one 256-cell step, per lane (4 cells): the wave's
 // exclusive prefix before the lane (Bex), the lane's own partial sums p1..p3
 // and the inclusive prefix B through the lane (running maximum: never
-// decreasing).  Staged in LDS by the first phase of the rescan.
+// decreasing).
 struct StepPrefix {
     f32x4 ex_p;   // Bex, p1, p2, p3
     float B;
 };
 
-// LDS of the staged prefixes of one tile: [steps][64] (Bex, p1, p2, p3) and
-// [steps][64] B, at most kMaxTileSteps steps
+// LDS of the staged prefixes of one tile: [steps][64] (Bex, p1, p2, p3).
+// B is not stored: B of a lane is Bex of the next lane, and B of the last
+// lane (the step total) is kept in the Bex slot of lane 0, whose Bex is 0 by
+// definition.  16 bytes per lane and step.
 struct Stage {
     f32x4* ex_p;
-    float* B;
-    __device__ void put(int i, const StepPrefix& p) {
-        ex_p[i] = p.ex_p;
-        B[i] = p.B;
+    __device__ void put(int s, const StepPrefix& p) {
+        f32x4 v = p.ex_p;
+        const float total = readlane(p.B, kWave - 1);
+        if (lane_id() == 0) v.x = total;
+        ex_p[s * kWave + lane_id()] = v;
     }
-    __device__ StepPrefix get(int i) const {
+    __device__ StepPrefix get(int s) const {
         StepPrefix p;
-        p.ex_p = ex_p[i];
-        p.B = B[i];
+        p.ex_p = ex_p[s * kWave + lane_id()];
+        p.B = __int_as_float(
+            __builtin_amdgcn_ds_bpermute(((lane_id() + 1) & (kWave - 1)) << 2, __float_as_int(p.ex_p.x)));
+        if (lane_id() == 0) p.ex_p.x = 0.0f;
         return p;
     }
 };
 
 constexpr int kBinWaves = kBinThreads / kWave;
 constexpr int kMaxTileSteps = 32;
-constexpr size_t kStageBytesPerStep = (size_t)kWave * (sizeof(f32x4) + sizeof(float));
+constexpr size_t kStageBytesPerStep = (size_t)kWave * sizeof(f32x4);
 
 // Phase 1 of the rescan, for the steps s = w, w + kBinWaves, ... of tile t
 // taken by wave w: f of every cell again (from values, cached entries or the
@@ -775,11 +780,12 @@ __device__ __forceinline__ void rescan_stage(const ReqDev& q, const JobDev& j, i
     int off[MT];
     table_offsets<MT>(q, M, off);
     if (w >= nsteps) return;
+    // two of this wave's steps in flight
     D cur, nxt;
+    const int s1 = min(w + kBinWaves, nsteps - 1);
     cur.load(view, M, w, gload<uint32_t>(view.lcode, w));
+    nxt.load(view, M, s1, gload<uint32_t>(view.lcode, s1));
     for (int s = w; s < nsteps; s += kBinWaves) {
-        const int sn = min(s + kBinWaves, nsteps - 1);
-        nxt.load(view, M, sn, gload<uint32_t>(view.lcode, sn));
         const int64_t quad = ((tbase + (int64_t)s * kStepCells) >> 2) + lane;
         float f[4];
 #pragma unroll
@@ -802,8 +808,10 @@ __device__ __forceinline__ void rescan_stage(const ReqDev& q, const JobDev& j, i
         sp.ex_p.z = p2;
         sp.ex_p.w = p3;
         sp.B = B;
-        stage.put(s * kWave + lane, sp);
+        stage.put(s, sp);
         cur = nxt;
+        const int sn = min(s + 2 * kBinWaves, nsteps - 1);
+        nxt.load(view, M, sn, gload<uint32_t>(view.lcode, sn));
     }
 }
 
@@ -834,7 +842,7 @@ __device__ __forceinline__ void rescan_walk(const ReqDev& q, const JobDev& j, in
     for (int s = 0; s < nsteps; ++s) {
         const int64_t c0 = tbase + (int64_t)s * kStepCells;
         const int64_t quad = (c0 >> 2) + lane;
-        const StepPrefix pr = stage.get(s * kWave + lane);
+        const StepPrefix pr = stage.get(s);
         const float Bex = pr.ex_p.x, p1 = pr.ex_p.y, p2 = pr.ex_p.z, p3 = pr.ex_p.w, B = pr.B;
         const float stot = readlane(B, kWave - 1);
         const bool full = c0 + kStepCells <= n;
@@ -967,7 +975,6 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
     const uint64_t* queue = bd.rescan_queue + IDX * bd.k3_units;
     Stage stage;
     stage.ex_p = reinterpret_cast<f32x4*>(tf_lds + ((bd.max_req_tf + 3) & ~3));
-    stage.B = reinterpret_cast<float*>(stage.ex_p + (size_t)bd.max_tile_steps * kWave);
 
     for (int64_t i = block_x(); i < n_queued; i += grid_dim_x()) {
         const int64_t u = uni((int64_t)gload<uint64_t>(queue, i));
@@ -1014,6 +1021,37 @@ __device__ __forceinline__ int64_t wave_partition_point(int64_t T, Pred pred) {
         lo = new_lo;
     }
     return lo;
+}
+
+// Two partition points of [0, T) at once (each predicate true on a prefix,
+// false after): lanes 0-31 probe `pa`, lanes 32-63 probe `pb`, 32 evenly
+// spaced points of each remaining range per round, so both searches finish
+// in the rounds one of them would take alone.
+template <typename PA, typename PB>
+__device__ __forceinline__ void wave_partition_points(int64_t T, PA pa, PB pb, int64_t& ra, int64_t& rb) {
+    const int lane = lane_id(), half = lane >> 5, l = lane & 31;
+    int64_t lo[2] = {0, 0}, hi[2] = {T, T};
+    while (lo[0] < hi[0] || lo[1] < hi[1]) {
+        const int64_t step0 = (hi[0] - lo[0] + 31) / 32, step1 = (hi[1] - lo[1] + 31) / 32;
+        const int64_t p = half == 0 ? lo[0] + step0 * l : lo[1] + step1 * l;
+        const bool t = half == 0 ? (p < hi[0] && pa(p)) : (p < hi[1] && pb(p));
+        const uint64_t m = __ballot(t);
+        const int c[2] = {(int)__popcll(m & 0xFFFFFFFFull), (int)__popcll(m >> 32)};
+        const int64_t step[2] = {step0, step1};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (lo[h] >= hi[h]) continue;
+            if (c[h] == 0) {
+                hi[h] = lo[h];                       // pred(lo) is false
+            } else {
+                const int64_t new_lo = lo[h] + step[h] * (c[h] - 1) + 1;
+                hi[h] = min(hi[h], lo[h] + step[h] * c[h]);
+                lo[h] = new_lo;
+            }
+        }
+    }
+    ra = lo[0];
+    rb = lo[1];
 }
 
 // Field statistics of the sorted cells [first, last], by one wave: the stored
@@ -1132,8 +1170,10 @@ __global__ __launch_bounds__(256) void k_bin_stats(BatchDev bd) {
     const int32_t* hb = q.ws.head_bin;
     const int32_t* tb = q.ws.tail_bin;
     // tiles touching bin b: t0 = first with tail >= b, t1 = last with head <= b
-    const int64_t t0 = wave_partition_point(T, [&](int64_t t) { return gload<int32_t>(tb, t) < b; });
-    const int64_t t1 = wave_partition_point(T, [&](int64_t t) { return gload<int32_t>(hb, t) <= b; }) - 1;
+    int64_t t0, t1;
+    wave_partition_points(T, [&](int64_t t) { return gload<int32_t>(tb, t) < b; },
+                          [&](int64_t t) { return gload<int32_t>(hb, t) <= b; }, t0, t1);
+    t1 -= 1;
     uint32_t first = 0xFFFFFFFFu, last = 0u;
     bool inside = false;
     if (t0 == t1) {

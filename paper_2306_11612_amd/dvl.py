@@ -158,6 +158,7 @@ def lib():
         "dvl_graph_create": (i32, [C.POINTER(dvl_request), i32, C.POINTER(vp)]),
         "dvl_graph_set_tf": (i32, [vp, i32, vp, vp, vp]),
         "dvl_graph_launch": (i32, [vp, vp]),
+        "dvl_graph_set_tf_all": (i32, [vp, vp, vp, vp]),
         "dvl_graph_destroy": (None, [vp]),
         "dvl_last_error": (C.c_char_p, []),
         "dvl_select_bins": (i32, [vp, C.POINTER(dvl_bins), i32, i32, i32, vp, vp, vp, vp, vp]),
@@ -573,6 +574,19 @@ class Graph:
         hi = None if hi is None else np.ascontiguousarray(np.asarray(hi, np.float32))
         P = lambda x: None if x is None else x.ctypes.data_as(C.c_void_p)
         _check(lib().dvl_graph_set_tf(self.handle, int(i), P(a), P(lo), P(hi)), "dvl_graph_set_tf")
+
+    def set_tf_all(self, alphas):
+        """dvl_graph_set_tf_all: new [M][n_tf] tables for every request (data-range windows)."""
+        arrs = []
+        for r, a in zip(self.reqs, alphas):
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+            if a.shape != r.alpha.shape:
+                raise ValueError(f"alpha must keep the shape {r.alpha.shape}")
+            arrs.append(a)
+        if len(arrs) != len(self.reqs):
+            raise ValueError("one table set per request")
+        ptrs = (C.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+        _check(lib().dvl_graph_set_tf_all(self.handle, C.cast(ptrs, C.c_void_p), None, None), "dvl_graph_set_tf_all")
 
     def launch(self, stream=None):
         _check(lib().dvl_graph_launch(self.handle, _stream_ptr(stream)), "dvl_graph_launch")

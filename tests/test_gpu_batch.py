@@ -188,10 +188,14 @@ def test_graph_replays_follow_tf_changes():
         try:
             for rep in range(4):
                 if rep:
-                    for i, r in enumerate(reqs):
-                        A = tfs(1000 * rep + i, 4)
+                    new = [tfs(1000 * rep + i, 4) for i in range(len(reqs))]
+                    for r, A in zip(reqs, new):
                         r.alpha = np.ascontiguousarray(A)
-                        g.set_tf(i, A)
+                    if rep % 2:
+                        g.set_tf_all(new)                    # one call for every request
+                    else:
+                        for i, A in enumerate(new):
+                            g.set_tf(i, A)
                 print(f"[graph] replay {rep}", flush=True)
                 g.launch()
                 junk = torch.randn(1 << 20, device="cuda").cumsum(0)     # unrelated eager work
