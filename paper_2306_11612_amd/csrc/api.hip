@@ -179,7 +179,8 @@ struct dvl_volume {
     // reads the cache first waits for the rebuild (`cache_ready`).
     hipEvent_t cache_ready = nullptr;
     bool cache_ready_recorded = false;
-    std::vector<std::pair<hipStream_t, hipEvent_t>> cache_readers;
+    hipStream_t cache_ready_stream = nullptr;   // where the last rebuild ran
+    std::vector<hipStream_t> cache_readers;     // streams whose launches read the cache
     // the volume's own transfer functions (used by dvl_update)
     bool tf_set[kMaxFields] = {};
     std::vector<float> alpha[kMaxFields];
@@ -605,11 +606,47 @@ static dvl_status decide_cache(Plan& P, std::vector<CacheBuild>& builds) {
 // still read a cache and later launches on any stream must see the new one;
 // both are ordered by events (see dvl_volume::cache_readers), so the host
 // never waits here.
+// One reader event per (device, stream), shared by every volume: re-recorded
+// after each launch on that stream that reads an entry cache.  A rebuild
+// waits for the latest record on each other reader stream, which follows
+// every earlier launch there (stream order): one record per launch instead
+// of one per volume, each of which is a queue packet.  The events live until
+// the process ends.
+struct ReaderEvent {
+    int dev;
+    hipStream_t s;
+    hipEvent_t ev;
+};
+static std::mutex g_reader_mu;
+static std::vector<ReaderEvent> g_readers;
+
+static dvl_status reader_event(hipStream_t s, bool create, hipEvent_t* out) {
+    *out = nullptr;
+    int dev = -1;
+    DVL_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_reader_mu);
+    for (const ReaderEvent& r : g_readers)
+        if (r.dev == dev && r.s == s) {
+            *out = r.ev;
+            return DVL_OK;
+        }
+    if (!create) return DVL_OK;
+    hipEvent_t ev = nullptr;
+    DVL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    g_readers.push_back({dev, s, ev});
+    *out = ev;
+    return DVL_OK;
+}
+
 static dvl_status run_cache_builds(const std::vector<CacheBuild>& builds, hipStream_t s) {
     for (const CacheBuild& cb : builds) {
         dvl_volume* v = cb.v;
-        for (auto& r : v->cache_readers)
-            if (r.first != s) DVL_HIP(hipStreamWaitEvent(s, r.second, 0));
+        for (hipStream_t r : v->cache_readers) {
+            if (r == s) continue;
+            hipEvent_t ev = nullptr;
+            if (dvl_status st = reader_event(r, false, &ev)) return st;
+            if (ev) DVL_HIP(hipStreamWaitEvent(s, ev, 0));
+        }
         v->idx_valid = false;
         for (int m = 0; m < v->M; ++m)
             if (dvl_status st = launch_build_index(v->n_pad, v->dtype, v->fields_s[m], cb.key.s[m], cb.key.b[m],
@@ -617,6 +654,7 @@ static dvl_status run_cache_builds(const std::vector<CacheBuild>& builds, hipStr
                 return st;
         DVL_HIP(hipEventRecord(v->cache_ready, s));
         v->cache_ready_recorded = true;
+        v->cache_ready_stream = s;
         v->idx_key = cb.key;
         v->idx_valid = true;
         v->cand_set = false;
@@ -625,30 +663,33 @@ static dvl_status run_cache_builds(const std::vector<CacheBuild>& builds, hipStr
 }
 
 // Before a launch on stream s that reads the caches of the jobs in `P`: wait
-// for their latest rebuild (done on another stream, possibly).
+// for their latest rebuild when it ran on another stream (on s itself the
+// stream order already follows it).
 static dvl_status cache_wait(const Plan& P, hipStream_t s) {
     for (const JobDev& j : P.jobs) {
         if (!j.idx[0]) continue;
         dvl_volume* v = P.reqs[j.req0].v;
-        if (v->cache_ready_recorded) DVL_HIP(hipStreamWaitEvent(s, v->cache_ready, 0));
+        if (v->cache_ready_recorded && v->cache_ready_stream != s)
+            DVL_HIP(hipStreamWaitEvent(s, v->cache_ready, 0));
     }
     return DVL_OK;
 }
 
-// After such a launch: remember it as the latest reader on stream s.
+// After such a launch: s is a reader stream of those volumes, and its reader
+// event is recorded once.
 static dvl_status cache_mark_readers(const Plan& P, hipStream_t s) {
+    bool any = false;
     for (const JobDev& j : P.jobs) {
         if (!j.idx[0]) continue;
         dvl_volume* v = P.reqs[j.req0].v;
-        hipEvent_t ev = nullptr;
-        for (auto& r : v->cache_readers)
-            if (r.first == s) ev = r.second;
-        if (!ev) {
-            DVL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-            v->cache_readers.push_back({s, ev});
-        }
-        DVL_HIP(hipEventRecord(ev, s));
+        if (std::find(v->cache_readers.begin(), v->cache_readers.end(), s) == v->cache_readers.end())
+            v->cache_readers.push_back(s);
+        any = true;
     }
+    if (!any) return DVL_OK;
+    hipEvent_t ev = nullptr;
+    if (dvl_status st = reader_event(s, true, &ev)) return st;
+    DVL_HIP(hipEventRecord(ev, s));
     return DVL_OK;
 }
 
@@ -1247,9 +1288,9 @@ static dvl_status poke(char* dst, const char* src, size_t bytes, hipStream_t s) 
 }
 
 // A job reads the volume's entry cache here only when the cache already holds
-// its key (it is never built here) and this stream already has a reader
-// event of the volume (re-recorded below), so a later rebuild elsewhere
-// still waits for this launch.
+// its key (it is never built here) and this stream is already one of the
+// volume's reader streams (its reader event exists and is re-recorded below,
+// creating nothing), so a later rebuild elsewhere still waits for this launch.
 static void use_existing_cache(Plan& P, hipStream_t s) {
     for (JobDev& j : P.jobs) {
         for (int m = 0; m < kMaxFields; ++m) j.idx[m] = nullptr;
@@ -1257,9 +1298,7 @@ static void use_existing_cache(Plan& P, hipStream_t s) {
         if (v->idx_policy == DVL_ENTRY_CACHE_NEVER || !v->idx_valid) continue;
         CacheKey key;
         if (!key_of(P.reqs[j.req0], key) || !(key == v->idx_key)) continue;
-        bool reader = false;
-        for (auto& r : v->cache_readers) reader = reader || r.first == s;
-        if (!reader) continue;
+        if (std::find(v->cache_readers.begin(), v->cache_readers.end(), s) == v->cache_readers.end()) continue;
         for (int m = 0; m < v->M; ++m) j.idx[m] = v->idx_s[m];
     }
 }
@@ -1300,10 +1339,13 @@ dvl_status dvl_update_noalloc(dvl_volume* v, const dvl_params* p, const dvl_bins
         if (st == DVL_E_HIP) v->sticky = st;
         return st;
     }
-    for (JobDev& j : P.jobs)
-        if (j.idx[0])
-            for (auto& r : P.reqs[j.req0].v->cache_readers)
-                if (r.first == s) DVL_HIP(hipEventRecord(r.second, s));
+    for (const JobDev& j : P.jobs)
+        if (j.idx[0]) {
+            hipEvent_t ev = nullptr;   // exists: s is a reader stream of the volume
+            if (dvl_status st = reader_event(s, false, &ev)) return st;
+            if (ev) DVL_HIP(hipEventRecord(ev, s));
+            break;
+        }
     return DVL_OK;
 }
 
@@ -1642,7 +1684,6 @@ void dvl_destroy(dvl_volume* v) {
     A.put(v->scratch_range, nullptr);
     for (int m = 0; m < kMaxFields; ++m) A.put(v->idx_s[m], nullptr);
     if (v->cache_ready) (void)hipEventDestroy(v->cache_ready);
-    for (auto& r : v->cache_readers) (void)hipEventDestroy(r.second);
     delete v;
 }
 

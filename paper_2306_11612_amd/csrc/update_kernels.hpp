@@ -65,11 +65,10 @@ __device__ __forceinline__ ImpCtx make_ctx(const ReqDev& q) {
     return c;
 }
 
-// TF entry: clamp(floor(fma(x, s, b)), 0, n_tf - 1)
+// TF entry: clamp(floor(fma(x, s, b)), 0, n_tf - 1); the clamp is one
+// median-of-three (nmax >= 1), the floor the truncation of a value >= 0
 __device__ __forceinline__ int tf_entry(float x, float s, float b, float nmax) {
-    float t = fmaf(x, s, b);
-    t = fminf(fmaxf(t, 0.0f), nmax);
-    return (int)t;
+    return (int)__builtin_amdgcn_fmed3f(fmaf(x, s, b), 0.0f, nmax);
 }
 
 // Eq. 1: V = max_m alpha_m(x_m) - min_m alpha_m(x_m); `tf` is the request's block
@@ -142,7 +141,12 @@ struct LaneLevels {
         lc = (code >> ((lane_id() >> 4) << 3)) & 0xFFu;
         lv = gload_at<uint32_t>(lev, lc == 0xFFu ? qd * 4u : 0u);
     }
-    __device__ __forceinline__ uint32_t get(int k) const { return lc == 0xFFu ? (lv >> (8 * k)) & 0xFFu : lc; }
+    // the 4 levels as the bytes of one word: the loaded ones, or the code's
+    // level in every byte (one select per step instead of one per cell)
+    __device__ __forceinline__ uint32_t word() const {
+        return lc == 0xFFu ? lv : __builtin_amdgcn_perm(0u, lc, 0u);
+    }
+    __device__ __forceinline__ uint32_t get(int k) const { return (word() >> (8 * k)) & 0xFFu; }
 };
 
 // values of the 4 cells of this lane in the given step
@@ -205,21 +209,55 @@ __device__ __forceinline__ RunView<MT> run_view(const JobDev& j, int M, int64_t 
 // V of cell k of this lane for request q, from values or from cached
 // entries; off[m]: start of field m's table in `tf` (the request's block)
 template <int MT, typename S>
-__device__ __forceinline__ float cell_v(const StepData<MT, S>& d, int k, int M, const float* tf, const ReqDev& q,
-                                        const int (&off)[MT]) {
+__device__ __forceinline__ float cell_v(const StepData<MT, S>& d, int k, int M, const float* lds0, const float* tf,
+                                        const ReqDev& q, const int (&off)[MT]) {
     float xk[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) xk[m] = m < M ? d.q[m].get(k) : 0.0f;
     return variation<MT>(xk, M, tf, q);
 }
+// 4 x byte k of w (the byte offset of an entry in its table), one
+// instruction through the byte operand select of the SDWA encoding
+__device__ __forceinline__ uint32_t entry_x4(uint32_t w, int k) {
+    uint32_t a;
+    switch (k) {
+    case 0:
+        asm("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+            : "=v"(a) : "v"(w));
+        break;
+    case 1:
+        asm("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+            : "=v"(a) : "v"(w));
+        break;
+    case 2:
+        asm("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+            : "=v"(a) : "v"(w));
+        break;
+    default:
+        asm("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+            : "=v"(a) : "v"(w));
+        break;
+    }
+    return a;
+}
+
+typedef __attribute__((address_space(3))) const float lds_f32;
+
+// lds0: the kernel's dynamic LDS array, which starts at LDS address 0 (the
+// kernels that take this path have no static LDS; their launcher checks), so
+// an entry's LDS address is its byte offset in the table plus the table's
+// compile-time offset, and the table offset lands in the instruction's
+// immediate.
 template <int MT>
-__device__ __forceinline__ float cell_v(const StepIdx<MT>& d, int k, int M, const float* tf, const ReqDev& q,
-                                        const int (&off)[MT]) {
+__device__ __forceinline__ float cell_v(const StepIdx<MT>& d, int k, int M, const float* lds0, const float* tf,
+                                        const ReqDev& q, const int (&off)[MT]) {
+    const uint32_t tb = (uint32_t)(tf - lds0) * (uint32_t)sizeof(float);
     float amax = -INFINITY, amin = INFINITY;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         if (m < M) {
-            const float al = tf[m * kIdxTable + (int)((d.e[m] >> (8 * k)) & 0xFFu)];
+            const uint32_t a = entry_x4(d.e[m], k) + tb + (uint32_t)(m * kIdxTable * sizeof(float));
+            const float al = *reinterpret_cast<lds_f32*>((uintptr_t)a);
             amax = fmaxf(amax, al);
             amin = fminf(amin, al);
         }
@@ -252,8 +290,11 @@ template <typename D> struct Group { static constexpr int n = 1; };
 #define DVL_ENTRY_GROUP 4
 #endif
 template <int MT> struct Group<StepIdx<MT>> { static constexpr int n = DVL_ENTRY_GROUP; };
-template <int MT> struct Group<StepData<MT, F16>> { static constexpr int n = 2; };
-template <int MT> struct Group<StepData<MT, BF16>> { static constexpr int n = 2; };
+#ifndef DVL_HALF_GROUP
+#define DVL_HALF_GROUP 2
+#endif
+template <int MT> struct Group<StepData<MT, F16>> { static constexpr int n = DVL_HALF_GROUP; };
+template <int MT> struct Group<StepData<MT, BF16>> { static constexpr int n = DVL_HALF_GROUP; };
 
 // level codes of the G steps of a group (step: its first, a multiple of G),
 // through vector loads (every lane the same words): they are waited for in
@@ -317,7 +358,7 @@ __device__ __forceinline__ void vmax_run(const BatchDev& b, const JobDev& j, int
 #pragma unroll
                 for (int q = 0; q < KR; ++q)
                     if (q < j.n_req && rq[q].vmax_exact)
-                        vmax[q] = fmaxf(vmax[q], cell_v<MT>(d[g], k, M, tf_lds + TableBase<MT, D>::of(q, toff[q]), rq[q], off[q]));
+                        vmax[q] = fmaxf(vmax[q], cell_v<MT>(d[g], k, M, tf_lds, tf_lds + TableBase<MT, D>::of(q, toff[q]), rq[q], off[q]));
             }
         }
     }
@@ -507,7 +548,7 @@ __device__ __forceinline__ void tile_sums_run(const BatchDev& b, const JobDev& j
                     float f[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const float v = cell_v<MT>(cur[g], k, M, tf_lds + TableBase<MT, D>::of(q, toff[q]), rq[q], off[q]);
+                        const float v = cell_v<MT>(cur[g], k, M, tf_lds, tf_lds + TableBase<MT, D>::of(q, toff[q]), rq[q], off[q]);
                         const uint32_t L = cur[g].lv.get(k);
                         f[k] = P1 ? importance_p1(v, L, ctx[q]) : importance_from_v(v, L, ctx[q]);
                     }
@@ -1084,9 +1125,10 @@ __device__ __forceinline__ void bin_range_stats(const JobDev& j, int M, uint32_t
         if (end == 1 && (sl == sf || wl)) break;
         const int64_t st = end == 0 ? sf : sl;
         const int64_t c = st * kStepCells + 4 * lane;
+        const bool need = c + 3 >= f && c <= l;     // lanes with no cell of the range fetch nothing
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
-            if (m < M) {
+            if (m < M && need) {
                 Quad<S> qd;
                 qd.load(j.fields[m], st * kWave + lane);
 #pragma unroll
@@ -1237,8 +1279,28 @@ __global__ __launch_bounds__(256) void k_bin_stats(BatchDev bd) {
 dvl_status launch_carry(const BatchDev& b, hipStream_t s);
 dvl_status launch_classify(const BatchDev& b, hipStream_t s);
 
+// The cached-entry importance kernels address their tables from LDS address
+// 0 (the start of the dynamic LDS array): they must hold no static LDS.
+template <void (*Kernel)(BatchDev)>
+static dvl_status check_no_static_lds(const char* name) {
+    static int checked = 0;   // one flag per kernel instance
+    if (checked == 1) return DVL_OK;
+    hipFuncAttributes fa;
+    DVL_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(Kernel)));
+    if (fa.sharedSizeBytes != 0) {
+        set_error("%s holds %zu bytes of static LDS; its table addressing needs none", name, (size_t)fa.sharedSizeBytes);
+        return DVL_E_HIP;
+    }
+    checked = 1;
+    return DVL_OK;
+}
+
 template <int MT, typename S, int KR>
 static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEvent_t* ev) {
+    if (b.paths & kPathEntries) {
+        if (dvl_status st = check_no_static_lds<k_tile_sums<MT, S, KR, 1>>("k_tile_sums")) return st;
+        if (dvl_status st = check_no_static_lds<k_vmax_exact<MT, S, KR, 1>>("k_vmax_exact")) return st;
+    }
     auto mark = [&](int i) -> dvl_status {
         if (ev) DVL_HIP(hipEventRecord(ev[i], s));
         return DVL_OK;
