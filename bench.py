@@ -165,6 +165,9 @@ def bench_batch32(args, dt):
     kw = dict(exponent=args.exponent, min_importance=args.min_importance)
 
     def timed(step, label):
+        """Pipelined wall-clock ms per step (the host runs ahead), then the
+        median per-step latency with the host waiting for each step (events
+        on the current stream around one step)."""
         for k in range(args.warmup):
             step(k)
         torch.cuda.synchronize()
@@ -173,8 +176,9 @@ def bench_batch32(args, dt):
             step(k)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        log(f"{label}: {ms:.3f} ms per step of {n_vol} updates")
-        return ms
+        lat = pct(event_times(step, max(args.steps, 10)))
+        log(f"{label}: {ms:.3f} ms per step of {n_vol} updates, latency p50 {lat['p50']:.3f} ms")
+        return ms, lat
 
     bins = [dvl.Bins(W, M) for _ in vols]
 
@@ -184,7 +188,7 @@ def bench_batch32(args, dt):
             for m in range(M):
                 V.set_tf(m, A[m])
             V.update(bins[i], **kw)
-    ms_seq = timed(seq, "sequential dvl_update")
+    ms_seq, lat_seq = timed(seq, "sequential dvl_update")
 
     ex = dvl.Executor()
     reqs = [dvl.Request(V, tfs[i][0], bins[i], **kw) for i, V in enumerate(vols)]
@@ -193,7 +197,7 @@ def bench_batch32(args, dt):
         for i, r in enumerate(reqs):
             r.alpha = np.ascontiguousarray(tfs[i][k & 1])
         ex.update_batch(reqs)
-    ms_batch = timed(batch, "dvl_update_batch")
+    ms_batch, lat_batch = timed(batch, "dvl_update_batch")
     ex.set_timing(True)
     ex.kernel_times()
     for k in range(args.steps):
@@ -209,7 +213,7 @@ def bench_batch32(args, dt):
     def graph(k):
         g.set_tf_all(alt[k & 1])
         g.launch()
-    ms_graph = timed(graph, "captured graph")
+    ms_graph, lat_graph = timed(graph, "captured graph")
     cached = all(V.entry_cache_info() is not None for V in vols)
     dom = max(("tile_sums", "bin", "bin_stats"), key=lambda k: per_launch[k])
     elem = 4 if args.dtype == "f32" else 2
@@ -251,6 +255,7 @@ def bench_batch32(args, dt):
                           for a, b in sorted(set(layouts))},
         "entry_cache": cached,
         "sequential_ms_per_step": ms_seq, "batch_ms_per_step": ms_batch, "graph_ms_per_step": ms_graph,
+        "step_latency_ms": {"sequential": lat_seq, "batch": lat_batch, "graph": lat_graph},
         "speedup_vs_sequential": ms_seq / ms_best,
         "kernel_ms_per_batch": per_launch, "generation_s": gen_s,
     }

@@ -926,7 +926,13 @@ struct dvl_graph {
     Plan plan;
     Alloc alloc;                         // the first request's volume's allocator
     int n_cu = 256;
-    char* dev = nullptr;                 // the descriptor block the captured kernels read
+    // two descriptor blocks, each read by its own captured graphs; launches
+    // alternate between them, so consecutive replays are different
+    // executable graphs (one executable graph is not replayed while its
+    // previous launch may still run)
+    static constexpr int kSlots = 2;
+    char* dev[kSlots] = {};
+    int launches = 0;
     std::vector<void*> ws;               // one workspace per request
     char* host[kRing] = {};              // pinned staging of the descriptor block
     hipEvent_t ev[kRing] = {};
@@ -937,6 +943,7 @@ struct dvl_graph {
     // use, and the set can change between launches as entry caches appear
     struct Captured {
         int paths;
+        int slot;
         hipGraph_t graph;
         hipGraphExec_t exec;
     };
@@ -947,7 +954,7 @@ struct dvl_graph {
             if (c.exec) (void)hipGraphExecDestroy(c.exec);
             if (c.graph) (void)hipGraphDestroy(c.graph);
         }
-        alloc.put(dev, nullptr);
+        for (char* d : dev) alloc.put(d, nullptr);
         for (void* w : ws) alloc.put(w, nullptr);
         for (int r = 0; r < kRing; ++r) {
             if (host[r]) (void)hipHostFree(host[r]);
@@ -1754,13 +1761,15 @@ dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph**
         g->ws.push_back(w.release());
         workspace_carve(g->ws.back(), r.v->n_tiles, r.v->M, fstore_cells(r.v, r.p.n_bins), &P.rdev[q].ws);
     }
-    DevBuf d(g->alloc);
-    if (dvl_status st = d.alloc(P.device_bytes, "graph descriptors")) return st;
-    g->dev = (char*)d.release();
+    for (int k = 0; k < dvl_graph::kSlots; ++k) {
+        DevBuf d(g->alloc);
+        if (dvl_status st = d.alloc(P.device_bytes, "graph descriptors")) return st;
+        g->dev[k] = (char*)d.release();
+    }
     {
         // a first descriptor image validates the tables (range checks) before anything is captured
         std::vector<char> probe(P.block_bytes);
-        if (dvl_status st = fill_block(P, probe.data(), g->dev)) return st;
+        if (dvl_status st = fill_block(P, probe.data(), g->dev[0])) return st;
     }
     for (int r = 0; r < kRing; ++r) {
         if (hipHostMalloc((void**)&g->host[r], P.block_bytes, hipHostMallocDefault) != hipSuccess) {
@@ -1778,9 +1787,9 @@ dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph**
 }
 
 // The executable graph of this path set, captured on first use.
-static dvl_status graph_exec_for(dvl_graph* g, int paths, hipGraphExec_t* out) {
+static dvl_status graph_exec_for(dvl_graph* g, int paths, int slot, hipGraphExec_t* out) {
     for (auto& c : g->captured)
-        if (c.paths == paths) {
+        if (c.paths == paths && c.slot == slot) {
             *out = c.exec;
             return DVL_OK;
         }
@@ -1792,7 +1801,7 @@ static dvl_status graph_exec_for(dvl_graph* g, int paths, hipGraphExec_t* out) {
         return hip_fail(e, "hipStreamBeginCapture");
     }
     const dvl_status cst =
-        launch_batch(batch_dev(P, g->dev, paths), P.dtype, P.max_m, P.max_req, g->n_cu, cs, kDescriptorLayout, nullptr);
+        launch_batch(batch_dev(P, g->dev[slot], paths), P.dtype, P.max_m, P.max_req, g->n_cu, cs, kDescriptorLayout, nullptr);
     hipGraph_t graph = nullptr;
     const hipError_t ee = hipStreamEndCapture(cs, &graph);
     (void)hipStreamDestroy(cs);
@@ -1806,7 +1815,7 @@ static dvl_status graph_exec_for(dvl_graph* g, int paths, hipGraphExec_t* out) {
         (void)hipGraphDestroy(graph);
         return hip_fail(e, "hipGraphInstantiate");
     }
-    g->captured.push_back({paths, graph, exec});
+    g->captured.push_back({paths, slot, graph, exec});
     *out = exec;
     return DVL_OK;
 }
@@ -1858,14 +1867,16 @@ dvl_status dvl_graph_launch(dvl_graph* g, void* stream) {
     for (const JobDev& j : g->plan.jobs) paths |= j.idx[0] ? kPathEntries : kPathValues;
     for (const ReqDev& d : g->plan.rdev)
         if (d.ws.fstore) paths |= kPathStoredF;
+    const int slot = g->launches % dvl_graph::kSlots;
     hipGraphExec_t exec = nullptr;
-    if (dvl_status st = graph_exec_for(g, paths, &exec)) return st;
-    if (dvl_status st = fill_block(g->plan, g->host[r], g->dev)) return st;
+    if (dvl_status st = graph_exec_for(g, paths, slot, &exec)) return st;
+    if (dvl_status st = fill_block(g->plan, g->host[r], g->dev[slot])) return st;
     g->next = (r + 1) % kRing;
-    DVL_HIP(hipMemcpyAsync(g->dev, g->host[r], g->plan.block_bytes, hipMemcpyHostToDevice, s));
+    DVL_HIP(hipMemcpyAsync(g->dev[slot], g->host[r], g->plan.block_bytes, hipMemcpyHostToDevice, s));
     DVL_HIP(hipEventRecord(g->ev[r], s));
     g->used[r] = true;
     DVL_HIP(hipGraphLaunch(exec, s));
+    ++g->launches;
     return cache_mark_readers(g->plan, s);
 }
 

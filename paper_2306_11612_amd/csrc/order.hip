@@ -117,7 +117,10 @@ __global__ __launch_bounds__(256) void k_keys(int64_t n, const int32_t* __restri
 
 // ===================================================================
 // LSD radix sort, 8-bit digits.  Per pass:
-//   k_digit_hist   per-tile digit counts, stored digit-major [256][T]
+//   k_digit_hist   per-tile digit counts, stored digit-major [256][T_pad]
+//                  (T_pad: tiles rounded up to a group of 16); one workgroup
+//                  counts 16 consecutive tiles and writes each digit's 16
+//                  counts as one contiguous 64-byte run
 //   scan_u32       exclusive scan of that array (global bucket offsets)
 //   k_scatter      stable in-tile ranking (wave match of equal digits),
 //                  staging of the tile in digit order in LDS, then writes of
@@ -128,31 +131,45 @@ constexpr int kSortItems = 16;                       // per thread
 constexpr int kSortTile = kSortThreads * kSortItems; // 4096 keys
 constexpr int kWavesPerSortTile = kSortThreads / kWave;
 constexpr int kRadix = 256;
+constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
+
+constexpr int kHistGroup = 16;   // tiles per k_digit_hist workgroup (64 B of counts per digit)
 
 __global__ __launch_bounds__(kSortThreads) void k_digit_hist(int64_t n, const uint64_t* __restrict__ keys,
-                                                             int shift, int64_t n_tiles,
+                                                             int shift, int64_t t_pad,
                                                              uint32_t* __restrict__ counts) {
     __shared__ uint32_t hist[kWavesPerSortTile][kRadix];
+    __shared__ uint32_t out[kRadix][kHistGroup];
     const int w = threadIdx.x / kWave;
-    for (int i = threadIdx.x; i < kWavesPerSortTile * kRadix; i += kSortThreads)
-        (&hist[0][0])[i] = 0;
-    __syncthreads();
-    const int64_t tile = blockIdx.x;
-    const int64_t base = tile * kSortTile;
+    const int64_t tile0 = (int64_t)blockIdx.x * kHistGroup;
+    for (int g = 0; g < kHistGroup; ++g) {
+        for (int i = threadIdx.x; i < kWavesPerSortTile * kRadix; i += kSortThreads)
+            (&hist[0][0])[i] = 0;
+        __syncthreads();
+        const int64_t base = (tile0 + g) * kSortTile;
 #pragma unroll 4
-    for (int r = 0; r < kSortItems; ++r) {
-        const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
-        if (i < n) {
-            const uint32_t d = (uint32_t)(keys[i] >> shift) & 0xFFu;
-            atomicAdd(&hist[w][d], 1u);
+        for (int r = 0; r < kSortItems; ++r) {
+            const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
+            if (i < n) {
+                const uint32_t d = (uint32_t)(keys[i] >> shift) & 0xFFu;
+                atomicAdd(&hist[w][d], 1u);
+            }
         }
-    }
-    __syncthreads();
-    for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
-        uint32_t s = 0;
+        __syncthreads();
+        for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
+            uint32_t c = 0;
 #pragma unroll
-        for (int q = 0; q < kWavesPerSortTile; ++q) s += hist[q][d];
-        counts[(int64_t)d * n_tiles + tile] = s;
+            for (int q = 0; q < kWavesPerSortTile; ++q) c += hist[q][d];
+            out[d][g] = c;
+        }
+        __syncthreads();
+    }
+    // digit d's counts of the group's 16 tiles: one 64-byte run
+    for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
+        uint4* dst = reinterpret_cast<uint4*>(counts + (int64_t)d * t_pad + tile0);
+#pragma unroll
+        for (int q = 0; q < kHistGroup / 4; ++q)
+            dst[q] = make_uint4(out[d][4 * q], out[d][4 * q + 1], out[d][4 * q + 2], out[d][4 * q + 3]);
     }
 }
 
@@ -248,7 +265,7 @@ int64_t scan_partial_count(int64_t n) { return (n + kScanBlock - 1) / kScanBlock
 
 __global__ __launch_bounds__(kSortThreads) void k_scatter(int64_t n, const uint64_t* __restrict__ kin,
                                                           const uint32_t* __restrict__ vin, int shift,
-                                                          int64_t n_tiles, const uint32_t* __restrict__ offs,
+                                                          int64_t t_pad, const uint32_t* __restrict__ offs,
                                                           uint64_t* __restrict__ kout,
                                                           uint32_t* __restrict__ vout) {
     __shared__ uint32_t whist[kWavesPerSortTile][kRadix];   // per-wave digit counts, then bases
@@ -262,7 +279,12 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(int64_t n, const uint6
 
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
-    const int64_t tile = blockIdx.x;
+    // Workgroups go to the 8 XCDs in turn; consecutive tiles on one XCD share
+    // the L2 lines of their digit offsets (16 tiles per 64-byte run), so XCD x
+    // takes the x-th contiguous eighth of the tiles.
+    const int64_t nb = gridDim.x, bid = blockIdx.x;
+    const int64_t xcd = bid % kXcds, per = nb / kXcds, rem = nb % kXcds;
+    const int64_t tile = xcd * per + min(xcd, rem) + bid / kXcds;
     const int64_t tbeg = tile * kSortTile;
     const int n_here = (int)min((int64_t)kSortTile, n - tbeg);
 
@@ -308,7 +330,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(int64_t n, const uint6
             run += c;
         }
         tbase[d] = run;   // tile count of digit d for now
-        gbase[d] = offs[(int64_t)d * n_tiles + tile];
+        gbase[d] = offs[(int64_t)d * t_pad + tile];
     }
     __syncthreads();
     // exclusive scan of the 256 tile counts (threads 0..255 hold one each)
@@ -379,18 +401,19 @@ dvl_status radix_sort(int64_t n, int key_bits, uint64_t* keys, uint32_t* vals, u
                       uint32_t* vals_tmp, uint32_t* counts, uint32_t* partial, hipStream_t s,
                       uint64_t** keys_out, uint32_t** vals_out) {
     const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+    const int64_t t_pad = sort_tile_count(n);
     const int passes = std::max(1, (key_bits + 7) / 8);
     uint64_t* ka = keys; uint64_t* kb = keys_tmp;
     uint32_t* va = vals; uint32_t* vb = vals_tmp;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, n, ka, shift,
-                           n_tiles, counts);
+        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)(t_pad / kHistGroup)), dim3(kSortThreads), 0, s, n, ka,
+                           shift, t_pad, counts);
         DVL_HIP(hipGetLastError());
-        dvl_status st = scan_u32(counts, counts, (int64_t)kRadix * n_tiles, partial, s);
+        dvl_status st = scan_u32(counts, counts, (int64_t)kRadix * t_pad, partial, s);
         if (st != DVL_OK) return st;
         hipLaunchKernelGGL(k_scatter, dim3((unsigned)n_tiles), dim3(kSortThreads), 0, s, n, ka, va, shift,
-                           n_tiles, counts, kb, vb);
+                           t_pad, counts, kb, vb);
         DVL_HIP(hipGetLastError());
         std::swap(ka, kb);
         std::swap(va, vb);
@@ -400,7 +423,10 @@ dvl_status radix_sort(int64_t n, int key_bits, uint64_t* keys, uint32_t* vals, u
     return DVL_OK;
 }
 
-int64_t sort_tile_count(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+int64_t sort_tile_count(int64_t n) {
+    const int64_t t = (n + kSortTile - 1) / kSortTile;
+    return (t + kHistGroup - 1) / kHistGroup * kHistGroup;
+}
 
 // ===================================================================
 // gather into sorted order; data ranges

@@ -14,7 +14,7 @@ dvl_status launch_keys(int64_t n, const int32_t* x, const int32_t* y, const int3
 dvl_status radix_sort(int64_t n, int key_bits, uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp,
                       uint32_t* vals_tmp, uint32_t* counts, uint32_t* partial, hipStream_t s,
                       uint64_t** keys_out, uint32_t** vals_out);
-int64_t sort_tile_count(int64_t n);        // tiles of the sort; counts needs 256 * tiles entries
+int64_t sort_tile_count(int64_t n);        // sort tiles rounded up to a group of 16; counts needs 256 * that
 int64_t scan_partial_count(int64_t n);     // partial sums the count scan needs for n entries
 dvl_status launch_dup(int64_t n, const uint64_t* keys, unsigned long long* flag, hipStream_t s);
 dvl_status launch_gather(int64_t n, const uint32_t* perm, const void* src, void* dst, int elem_bytes,
