@@ -130,6 +130,33 @@ struct CacheKey {
     }
 };
 
+// Small uploads through kernel arguments: k_poke writes up to kPokeWords
+// words carried in its arguments, so the copy runs in the stream's own queue
+// (no copy engine, no memcpy or memset node).
+constexpr int kPokeWords = 768;
+struct PokeArgs {
+    uint32_t* dst;
+    uint32_t n;
+    uint32_t w[kPokeWords];
+};
+
+__global__ __launch_bounds__(256) void k_poke(PokeArgs a) {
+    for (uint32_t i = threadIdx.x; i < a.n; i += blockDim.x) a.dst[i] = a.w[i];
+}
+
+static dvl_status poke(char* dst, const char* src, size_t bytes, hipStream_t s) {
+    const size_t nw = bytes / 4;
+    PokeArgs a;
+    for (size_t i = 0; i < nw; i += kPokeWords) {
+        a.dst = reinterpret_cast<uint32_t*>(dst) + i;
+        a.n = (uint32_t)std::min<size_t>(kPokeWords, nw - i);
+        memcpy(a.w, src + 4 * i, (size_t)a.n * 4);
+        hipLaunchKernelGGL(k_poke, dim3(1), dim3(256), 0, s, a);
+        DVL_HIP(hipGetLastError());
+    }
+    return DVL_OK;
+}
+
 struct Executor;
 
 }  // namespace dvl
@@ -856,7 +883,14 @@ struct Executor {
         Slot* slot = nullptr;
         if (dvl_status st = take_slot(P.device_bytes, &slot)) return st;
         if (dvl_status st = fill_block(P, slot->host, slot->dev)) return st;
-        DVL_HIP(hipMemcpyAsync(slot->dev, slot->host, P.block_bytes, hipMemcpyHostToDevice, s));
+#ifndef DVL_POKE_UPLOAD_MAX
+#define DVL_POKE_UPLOAD_MAX 0
+#endif
+        if (P.block_bytes <= (size_t)DVL_POKE_UPLOAD_MAX) {
+            if (dvl_status st = poke(slot->dev, slot->host, P.block_bytes, s)) return st;
+        } else {
+            DVL_HIP(hipMemcpyAsync(slot->dev, slot->host, P.block_bytes, hipMemcpyHostToDevice, s));
+        }
         DVL_HIP(hipEventRecord(slot->ev, s));
         slot->used = true;
         hipEvent_t* ev = nullptr;
@@ -1270,29 +1304,6 @@ static dvl_status scratch_address(int dev, char** out) {
 
 // Upload of a host image into device memory through kernel arguments (the
 // runtime copies them at launch): no staging buffer, no memcpy node.
-constexpr int kPokeWords = 768;
-struct PokeArgs {
-    uint32_t* dst;
-    uint32_t n;
-    uint32_t w[kPokeWords];
-};
-
-__global__ __launch_bounds__(256) void k_poke(PokeArgs a) {
-    for (uint32_t i = threadIdx.x; i < a.n; i += blockDim.x) a.dst[i] = a.w[i];
-}
-
-static dvl_status poke(char* dst, const char* src, size_t bytes, hipStream_t s) {
-    const size_t nw = bytes / 4;
-    PokeArgs a;
-    for (size_t i = 0; i < nw; i += kPokeWords) {
-        a.dst = reinterpret_cast<uint32_t*>(dst) + i;
-        a.n = (uint32_t)std::min<size_t>(kPokeWords, nw - i);
-        memcpy(a.w, src + 4 * i, (size_t)a.n * 4);
-        hipLaunchKernelGGL(k_poke, dim3(1), dim3(256), 0, s, a);
-        DVL_HIP(hipGetLastError());
-    }
-    return DVL_OK;
-}
 
 // A job reads the volume's entry cache here only when the cache already holds
 // its key (it is never built here) and this stream is already one of the
@@ -1693,6 +1704,7 @@ void dvl_destroy(dvl_volume* v) {
     if (v->cache_ready) (void)hipEventDestroy(v->cache_ready);
     delete v;
 }
+
 
 // ------------------------------------------------------------------ executors and batches
 
