@@ -130,9 +130,9 @@ struct CacheKey {
     }
 };
 
-// Small uploads through kernel arguments: k_poke writes up to kPokeWords
-// words carried in its arguments, so the copy runs in the stream's own queue
-// (no copy engine, no memcpy or memset node).
+// Uploads through kernel arguments (the allocation-free entry point): k_poke
+// writes up to kPokeWords words carried in its arguments, in the stream's own
+// queue (no memcpy or memset node).
 constexpr int kPokeWords = 768;
 struct PokeArgs {
     uint32_t* dst;
@@ -883,14 +883,7 @@ struct Executor {
         Slot* slot = nullptr;
         if (dvl_status st = take_slot(P.device_bytes, &slot)) return st;
         if (dvl_status st = fill_block(P, slot->host, slot->dev)) return st;
-#ifndef DVL_POKE_UPLOAD_MAX
-#define DVL_POKE_UPLOAD_MAX 0
-#endif
-        if (P.block_bytes <= (size_t)DVL_POKE_UPLOAD_MAX) {
-            if (dvl_status st = poke(slot->dev, slot->host, P.block_bytes, s)) return st;
-        } else {
-            DVL_HIP(hipMemcpyAsync(slot->dev, slot->host, P.block_bytes, hipMemcpyHostToDevice, s));
-        }
+        DVL_HIP(hipMemcpyAsync(slot->dev, slot->host, P.block_bytes, hipMemcpyHostToDevice, s));
         DVL_HIP(hipEventRecord(slot->ev, s));
         slot->used = true;
         hipEvent_t* ev = nullptr;

@@ -188,6 +188,7 @@ __device__ __forceinline__ T gload_at(const char* base, uint32_t byte_off) {
 // The constant address space (the dispatch packet is read through it).
 #define DVL_CONST __attribute__((address_space(4)))
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 // Work-item and work-group indices from the hardware and the dispatch packet.
 // The kernels of the update run in non-IEEE float mode, which keeps the

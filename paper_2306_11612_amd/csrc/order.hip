@@ -115,6 +115,88 @@ __global__ __launch_bounds__(256) void k_keys(int64_t n, const int32_t* __restri
     }
 }
 
+// The same two passes over four consecutive cells per thread and iteration
+// (x, y, z 16-byte aligned and level 4-byte aligned, checked by the
+// launchers): vector loads of the coordinates and levels, vector stores of
+// the keys and indices; the last n % 4 cells one by one.
+__device__ __forceinline__ void extent_add(int32_t cx, int32_t cy, int32_t cz, uint32_t L, int64_t& mx,
+                                           uint32_t& bad, uint32_t& lmax) {
+    bad |= (cx < 0) | (cy < 0) | (cz < 0) | (L > 20u);
+    lmax = max(lmax, L);
+    const int64_t w = (int64_t)1 << (L & 31u);
+    mx = max(mx, max(max((int64_t)cx, (int64_t)cy), (int64_t)cz) + w);
+}
+
+__global__ __launch_bounds__(256) void k_extent4(int64_t n, const int32_t* __restrict__ x,
+                                                 const int32_t* __restrict__ y,
+                                                 const int32_t* __restrict__ z,
+                                                 const uint8_t* __restrict__ level,
+                                                 unsigned long long* __restrict__ out) {
+    int64_t mx = 0;
+    uint32_t bad = 0, lmax = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nq = n >> 2;
+    for (int64_t q = tid; q < nq; q += stride) {
+        const int4 cx = reinterpret_cast<const int4*>(x)[q];
+        const int4 cy = reinterpret_cast<const int4*>(y)[q];
+        const int4 cz = reinterpret_cast<const int4*>(z)[q];
+        const uint32_t lw = reinterpret_cast<const uint32_t*>(level)[q];
+        extent_add(cx.x, cy.x, cz.x, lw & 0xFFu, mx, bad, lmax);
+        extent_add(cx.y, cy.y, cz.y, (lw >> 8) & 0xFFu, mx, bad, lmax);
+        extent_add(cx.z, cy.z, cz.z, (lw >> 16) & 0xFFu, mx, bad, lmax);
+        extent_add(cx.w, cy.w, cz.w, lw >> 24, mx, bad, lmax);
+    }
+    for (int64_t i = 4 * nq + tid; i < n; i += stride) extent_add(x[i], y[i], z[i], level[i], mx, bad, lmax);
+    for (int o = 32; o > 0; o >>= 1) {
+        const int l = lane_id() ^ o;
+        int lo = __builtin_amdgcn_ds_bpermute(l << 2, (int)(uint32_t)mx);
+        int hi = __builtin_amdgcn_ds_bpermute(l << 2, (int)(uint32_t)((uint64_t)mx >> 32));
+        mx = max(mx, (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+        bad |= (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)bad);
+        lmax = max(lmax, (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)lmax));
+    }
+    if (lane_id() == 0) {
+        atomicMax(&out[0], (unsigned long long)mx);
+        if (bad) atomicOr(&out[1], 1ull);
+        atomicMax(&out[2], (unsigned long long)lmax);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_keys4(int64_t n, const int32_t* __restrict__ x,
+                                               const int32_t* __restrict__ y,
+                                               const int32_t* __restrict__ z,
+                                               const uint8_t* __restrict__ level, int bits,
+                                               uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nq = n >> 2;
+    for (int64_t q = tid; q < nq; q += stride) {
+        const int4 cx = reinterpret_cast<const int4*>(x)[q];
+        const int4 cy = reinterpret_cast<const int4*>(y)[q];
+        const int4 cz = reinterpret_cast<const int4*>(z)[q];
+        const uint32_t lw = reinterpret_cast<const uint32_t*>(level)[q];
+        const int32_t xs[4] = {cx.x, cx.y, cx.z, cx.w}, ys[4] = {cy.x, cy.y, cy.z, cy.w},
+                      zs[4] = {cz.x, cz.y, cz.z, cz.w};
+        uint64_t k4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t half = (1u << ((lw >> (8 * k)) & 0xFFu)) >> 1;
+            k4[k] = hilbert3((uint32_t)xs[k] + half, (uint32_t)ys[k] + half, (uint32_t)zs[k] + half, bits);
+        }
+        u64x2* kd = reinterpret_cast<u64x2*>(keys + 4 * q);
+        kd[0] = u64x2{k4[0], k4[1]};
+        kd[1] = u64x2{k4[2], k4[3]};
+        const uint32_t i0 = (uint32_t)(4 * q);
+        reinterpret_cast<u32x4*>(idx)[q] = u32x4{i0, i0 + 1, i0 + 2, i0 + 3};
+    }
+    for (int64_t i = 4 * nq + tid; i < n; i += stride) {
+        const uint32_t half = (1u << level[i]) >> 1;
+        keys[i] = hilbert3((uint32_t)x[i] + half, (uint32_t)y[i] + half, (uint32_t)z[i] + half, bits);
+        idx[i] = (uint32_t)i;
+    }
+}
+
 // ===================================================================
 // LSD radix sort, 8-bit digits.  Per pass:
 //   k_digit_hist   per-tile digit counts, stored digit-major [256][T_pad]
@@ -432,10 +514,28 @@ int64_t sort_tile_count(int64_t n) {
 // gather into sorted order; data ranges
 // ===================================================================
 template <typename T>
+struct alignas(4 * sizeof(T)) Four {
+    T v[4];
+};
+
+// dst[i] = src[perm[i]]; four consecutive i per thread and iteration (perm and
+// dst are the volume's own, 256-byte aligned): one 16-byte load of perm, four
+// scattered loads in flight together, one vector store
+template <typename T>
 __global__ __launch_bounds__(256) void k_gather(int64_t n, const uint32_t* __restrict__ perm,
                                                 const T* __restrict__ src, T* __restrict__ dst) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nq = n >> 2;
+    for (int64_t q = tid; q < nq; q += stride) {
+        const u32x4 p = *reinterpret_cast<const u32x4*>(perm + 4 * q);
+        const uint32_t pk[4] = {p.x, p.y, p.z, p.w};
+        Four<T> o;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o.v[k] = pk[k] < (uint64_t)n ? src[pk[k]] : T(0);
+        reinterpret_cast<Four<T>*>(dst)[q] = o;
+    }
+    for (int64_t i = 4 * nq + tid; i < n; i += stride) {
         const uint32_t p = perm[i];
         if (p < (uint64_t)n) dst[i] = src[p];
     }
@@ -471,23 +571,48 @@ __global__ __launch_bounds__(256) void k_range(int64_t n, const typename S::raw*
 // gather of one field into sorted order fused with its data range (the
 // order-preserving uint map of k_range; out[0] min, out[1] max, out[2] NaN)
 template <typename S>
+__device__ __forceinline__ void range_add(float f, uint32_t& lo, uint32_t& hi, uint32_t& nan) {
+    if (f != f) {
+        nan = 1u;
+        return;
+    }
+    uint32_t u = __float_as_uint(f);
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    lo = min(lo, u);
+    hi = max(hi, u);
+}
+
+// Four consecutive sorted cells per thread and iteration: one 16-byte load of
+// their permutation entries, then the four (scattered) value loads in flight
+// together, one vector store; the last n % 4 cells one by one.
+template <typename S>
 __global__ __launch_bounds__(256) void k_gather_range(int64_t n, const uint32_t* __restrict__ perm,
                                                       const typename S::raw* __restrict__ src,
                                                       typename S::raw* __restrict__ dst,
                                                       unsigned int* __restrict__ out) {
+    using raw = typename S::raw;
     uint32_t lo = 0xFFFFFFFFu, hi = 0u, nan = 0u;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nq = n >> 2;
+    for (int64_t q = tid; q < nq; q += stride) {
+        const u32x4 p = *reinterpret_cast<const u32x4*>(perm + 4 * q);
+        const uint32_t pk[4] = {p.x, p.y, p.z, p.w};
+        raw r[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = pk[k] < (uint64_t)n ? src[pk[k]] : raw(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            dst[4 * q + k] = r[k];
+            if (pk[k] < (uint64_t)n) range_add<S>(to_f32(S{}, r[k]), lo, hi, nan);
+        }
+    }
+    for (int64_t i = 4 * nq + tid; i < n; i += stride) {
         const uint32_t p = perm[i];
         if (p >= (uint64_t)n) continue;
-        const typename S::raw r = src[p];
+        const raw r = src[p];
         dst[i] = r;
-        const float f = to_f32(S{}, r);
-        if (f != f) { nan = 1u; continue; }
-        uint32_t u = __float_as_uint(f);
-        u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-        lo = min(lo, u);
-        hi = max(hi, u);
+        range_add<S>(to_f32(S{}, r), lo, hi, nan);
     }
     for (int o = 32; o > 0; o >>= 1) {
         const int l = lane_id() ^ o;
@@ -517,16 +642,28 @@ static unsigned grid_for(int64_t n, int per_block = 256, int max_blocks = 8192) 
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, max_blocks));
 }
 
+// the caller's coordinate and level arrays allow the 4-cell loads
+static bool vec4_inputs(const int32_t* x, const int32_t* y, const int32_t* z, const uint8_t* level) {
+    return ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(z)) & 15u) == 0 &&
+           (reinterpret_cast<uintptr_t>(level) & 3u) == 0;
+}
+
 dvl_status launch_extent(int64_t n, const int32_t* x, const int32_t* y, const int32_t* z,
                          const uint8_t* level, unsigned long long* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_extent, dim3(grid_for(n)), dim3(256), 0, s, n, x, y, z, level, out);
+    if (vec4_inputs(x, y, z, level))
+        hipLaunchKernelGGL(k_extent4, dim3(grid_for((n + 3) / 4)), dim3(256), 0, s, n, x, y, z, level, out);
+    else
+        hipLaunchKernelGGL(k_extent, dim3(grid_for(n)), dim3(256), 0, s, n, x, y, z, level, out);
     DVL_HIP(hipGetLastError());
     return DVL_OK;
 }
 
 dvl_status launch_keys(int64_t n, const int32_t* x, const int32_t* y, const int32_t* z,
                        const uint8_t* level, int bits, uint64_t* keys, uint32_t* idx, hipStream_t s) {
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(256), 0, s, n, x, y, z, level, bits, keys, idx);
+    if (vec4_inputs(x, y, z, level))
+        hipLaunchKernelGGL(k_keys4, dim3(grid_for((n + 3) / 4)), dim3(256), 0, s, n, x, y, z, level, bits, keys, idx);
+    else
+        hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(256), 0, s, n, x, y, z, level, bits, keys, idx);
     DVL_HIP(hipGetLastError());
     return DVL_OK;
 }

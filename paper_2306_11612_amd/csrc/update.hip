@@ -308,34 +308,43 @@ __global__ __launch_bounds__(kUpdThreads) void k_tile_aggregates(int64_t n, cons
         const int64_t tbase = t * tile_steps * (int64_t)kStepCells;
         double acc = 0.0;
         float lo = INFINITY, hi = -INFINITY;
-        for (int st = 0; st < tile_steps; ++st) {
-            const int64_t quad = ((tbase + (int64_t)st * kStepCells) >> 2) + lane;
-            Quad<S> q;
-            q.load(field, quad);
-            float s4 = 0.0f;
-            double d4 = 0.0;
-            float slo = INFINITY, shi = -INFINITY;
+        // four steps' loads in flight together (tile_steps is a multiple of 4);
+        // the arithmetic runs step after step as in a plain loop
+        for (int st0 = 0; st0 < tile_steps; st0 += 4) {
+            const int64_t quad0 = ((tbase + (int64_t)st0 * kStepCells) >> 2) + lane;
+            Quad<S> qs[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if ((quad << 2) + k < n) {
-                    const float v = q.get(k);
-                    s4 += v;
-                    d4 += (double)v;
-                    slo = fminf(slo, v);
-                    shi = fmaxf(shi, v);
+            for (int g = 0; g < 4; ++g) qs[g].load(field, quad0 + (int64_t)g * kWave);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int st = st0 + g;
+                const int64_t quad = quad0 + (int64_t)g * kWave;
+                const Quad<S>& q = qs[g];
+                float s4 = 0.0f;
+                double d4 = 0.0;
+                float slo = INFINITY, shi = -INFINITY;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if ((quad << 2) + k < n) {
+                        const float v = q.get(k);
+                        s4 += v;
+                        d4 += (double)v;
+                        slo = fminf(slo, v);
+                        shi = fmaxf(shi, v);
+                    }
                 }
-            }
-            acc += (double)s4;
-            lo = fminf(lo, slo);
-            hi = fmaxf(hi, shi);
-            d4 = wave_sum_d(d4);
-            slo = wave_min_f(slo);
-            shi = wave_max_f(shi);
-            if (lane == 0) {
-                const int64_t gs = t * tile_steps + st;
-                ssum[gs] = d4;
-                smn[gs] = slo;
-                smx[gs] = shi;
+                acc += (double)s4;
+                lo = fminf(lo, slo);
+                hi = fmaxf(hi, shi);
+                d4 = wave_sum_d(d4);
+                slo = wave_min_f(slo);
+                shi = wave_max_f(shi);
+                if (lane == 0) {
+                    const int64_t gs = t * tile_steps + st;
+                    ssum[gs] = d4;
+                    smn[gs] = slo;
+                    smx[gs] = shi;
+                }
             }
         }
         acc = wave_sum_d(acc);
