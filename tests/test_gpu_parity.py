@@ -54,6 +54,29 @@ def test_order_ragged_sizes(n):
         V.close()
 
 
+@pytest.mark.parametrize("offset", [0, 1, 3])
+def test_order_from_offset_views(offset):
+    """Coordinates and levels passed as views that start `offset` elements into
+    larger buffers: unaligned starts take the one-cell-per-thread key and extent
+    kernels, aligned ones the four-cell kernels; the order is the same."""
+    D = dvl()
+    vol = subset(random_amr(11, 12, 3, 0.3), 9001, seed=offset)
+    n = vol.n
+    def shifted(t):
+        big = torch.zeros(n + 8, dtype=t.dtype, device="cuda")
+        big[offset:offset + n] = t.to("cuda")
+        return big[offset:offset + n]
+    x, y, z, lev = (shifted(t) for t in (vol.x, vol.y, vol.z, vol.level))
+    assert (x.data_ptr() % 16 == 0) == (offset == 0)
+    fields = [f.to("cuda") for f in vol.fields]
+    print(f"[order] offset={offset} n={n}", flush=True)
+    V = D.build_order(x, y, z, lev, fields)
+    try:
+        check_order(V, vol)
+    finally:
+        V.close()
+
+
 def test_order_cfg1_grid():
     import synth
     D = dvl()
