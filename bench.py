@@ -279,8 +279,8 @@ def sort_passes(bits: int) -> int:
 
 def ordering_bytes_per_cell(bits: int, M: int, elem: int) -> float:
     """Algorithmic bytes of the one-time ordering per cell: keys (read x, y, z,
-    level; write key and index: 13 + 12 - 4 = 21 B as counted for the survey's
-    table), the sort (one 8 B digit read per pass for the counts plus 24 B of
+    level: 13 B; write the 8-byte key: 21 B per cell, the 4-byte starting index
+    written beside it not counted), the sort (one 8 B digit read per pass for the counts plus 24 B of
     key and index read and written per pass), the gather of level and fields
     (read index, level, fields; write level and fields)."""
     p = sort_passes(bits)
@@ -494,7 +494,8 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "n_cells": n, "n_fields": M,
                    "field_storage": args.dtype, "n_bins": args.bins, "exponent": args.exponent,
                    "min_importance": args.min_importance, "tf_control_points": 4,
-                   "step": "TF change (dvl_set_tf x M with the windows kept) + dvl_update"},
+                   "step": "TF change (dvl_set_tf x M with the windows kept) + dvl_update",
+                   "layout": "library default: 4096-cell tiles (16 steps of 256 cells), default runs per wave"},
         "roofline": {"bound": "hbm", "kernel": dom + ("[entries]" if cached and dom == "tile_sums" else ""),
                      "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
