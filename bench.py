@@ -416,7 +416,9 @@ def main():
         for k in range(args.warmup):
             step(k)
         torch.cuda.synchronize()
-        V.set_timing(True)
+        # timed region: HIP events around the importance pass (the dominant
+        # kernel) of every update, two per update
+        V.set_timing(2)
         V.kernel_times()   # reset
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -424,8 +426,15 @@ def main():
             step(k)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        phases, n_upd = V.kernel_times()
+        k1_phases, n_upd = V.kernel_times()
+        # the other kernels, with events around each, over as many untimed steps
+        V.set_timing(1)
+        for k in range(args.steps):
+            step(k)
+        phases, n_all = V.kernel_times()
         V.set_timing(False)
+        phases = {k: v / max(n_all, 1) * max(n_upd, 1) for k, v in phases.items()}
+        phases["tile_sums"] = k1_phases["tile_sums"]
         ms = wall * 1e3 / args.steps
         cached = V.entry_cache_info() is not None
         log(f"entry cache {'on' if cached else 'off'}: {args.steps} steps in {wall:.3f} s: {ms:.3f} ms/update; "

@@ -433,15 +433,18 @@ dvl_status dvl_rasterize(const float* y, int32_t n_lines, int32_t n_bins, int32_
                          uint8_t* image, void* stream);
 
 /* ---------------------------------------------------------------------
- * Per-kernel timing of updates (profiling aid).  While enabled, every
+ * Per-kernel timing of updates (profiling aid).  With enable = 1, every
  * dvl_update records HIP events on its stream around each of its kernels:
  * phase 0 exact max(V) (VMAX_EXACT only), 1 tile sums of the importance,
  * 2 carry scan, 3 projection (tile classification and rescan: bin cell
- * ranges), 4 bin statistics (mean, min, max, height per bin).
+ * ranges), 4 bin statistics (mean, min, max, height per bin).  With
+ * enable = 2 only the two events around phase 1 (the importance pass, the
+ * dominant kernel) are recorded; the other phases read 0.  0 disables;
+ * other values return DVL_E_INVALID.
  * dvl_kernel_times synchronises on the recorded events, returns the summed
  * milliseconds per phase (ms[5]) over the updates since the last call and
- * their number, and resets the sums.  Enabling adds a few microseconds per
- * update.
+ * their number, and resets the sums.  Each recorded event adds a few
+ * microseconds to an update.
  * ------------------------------------------------------------------- */
 dvl_status dvl_set_timing(dvl_volume* v, int32_t enable);
 dvl_status dvl_kernel_times(dvl_volume* v, double* ms, int32_t* n_updates);

@@ -702,9 +702,9 @@ static dvl_status cache_wait(const Plan& P, hipStream_t s) {
     return DVL_OK;
 }
 
-// After such a launch: s is a reader stream of those volumes, and its reader
-// event is recorded once.
-static dvl_status cache_mark_readers(const Plan& P, hipStream_t s) {
+// After such a launch: s is a reader stream of those volumes (returns
+// whether any job read a cache).  The caller records s's reader event.
+static bool cache_add_readers(const Plan& P, hipStream_t s) {
     bool any = false;
     for (const JobDev& j : P.jobs) {
         if (!j.idx[0]) continue;
@@ -713,7 +713,12 @@ static dvl_status cache_mark_readers(const Plan& P, hipStream_t s) {
             v->cache_readers.push_back(s);
         any = true;
     }
-    if (!any) return DVL_OK;
+    return any;
+}
+
+// ... and records its reader event once when one did
+static dvl_status cache_mark_readers(const Plan& P, hipStream_t s) {
+    if (!cache_add_readers(P, s)) return DVL_OK;
     hipEvent_t ev = nullptr;
     if (dvl_status st = reader_event(s, true, &ev)) return st;
     DVL_HIP(hipEventRecord(ev, s));
@@ -747,7 +752,7 @@ static int64_t fstore_cells(const dvl_volume* v, int n_bins) {
     return wants_fstore(v->n_tiles, n_bins) ? v->n_pad : 0;
 }
 static size_t request_ws_bytes(const dvl_volume* v, int n_bins) {
-    return workspace_bytes(v->n_tiles, v->M, fstore_cells(v, n_bins));
+    return workspace_bytes(v->n_tiles, v->M, n_bins, fstore_cells(v, n_bins));
 }
 
 // ================================================================== executor
@@ -755,33 +760,32 @@ static size_t request_ws_bytes(const dvl_volume* v, int n_bins) {
 struct Executor {
     int n_cu = 256;
     Alloc alloc;                    // workspaces and descriptor blocks
-    struct Slot {
-        char* host = nullptr;
-        char* dev = nullptr;
-        size_t cap = 0;
-        hipEvent_t ev = nullptr;
-        bool used = false;
-    };
-    Slot ring[kRing];
-    int next = 0;
+    // The descriptor block: one device buffer, written before each launch by
+    // k_poke from a host image carried in kernel arguments (no staging
+    // buffer whose reuse the host would have to wait for).  Launches on one
+    // stream run in order, so a launch rewrites the block only after the
+    // previous launch's kernels have read it.
+    char* blk = nullptr;
+    size_t blk_cap = 0;
+    std::vector<char> img;
     std::vector<std::pair<void*, size_t>> ws;   // workspace pool: one per request position
-    hipEvent_t last = nullptr;      // end of this executor's latest launch
+    // The end of the latest launch is marked by the reader event of its
+    // stream (reader_event), recorded after every launch: it serves the
+    // entry-cache ordering and this executor alike, one queue packet.
+    hipStream_t last_stream = nullptr;
     bool launched = false;
-    bool timing = false;
+    int timing = 0;                 // 0 off, 1 every phase, 2 the importance pass only
     std::vector<std::vector<hipEvent_t>> ev_pool, ev_pending;
+    std::vector<int> ev_mode;       // the timing mode of each pending event set
+    std::vector<hipEvent_t> ev_sel; // the events handed to the launcher (unused phases NULL)
     double phase_ms[kPhases] = {};
     int32_t timed = 0;
     size_t bytes = 0;
 
     ~Executor() {
         (void)hipDeviceSynchronize();
-        for (auto& s : ring) {
-            if (s.host) (void)hipHostFree(s.host);
-            alloc.put(s.dev, nullptr);
-            if (s.ev) (void)hipEventDestroy(s.ev);
-        }
+        alloc.put(blk, nullptr);
         for (auto& w : ws) alloc.put(w.first, nullptr);
-        if (last) (void)hipEventDestroy(last);
         for (auto* pool : {&ev_pool, &ev_pending})
             for (auto& set : *pool)
                 for (auto e : set) (void)hipEventDestroy(e);
@@ -791,15 +795,23 @@ struct Executor {
         int dev = 0;
         DVL_HIP(hipGetDevice(&dev));
         DVL_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-        for (auto& s : ring) DVL_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
-        DVL_HIP(hipEventCreateWithFlags(&last, hipEventDisableTiming));
         return DVL_OK;
     }
 
-    // the executor's earlier launches (one stream) are the only users of its
-    // buffers: waiting for the latest one frees them for reuse
+    // the end of the latest launch (the reader event of its stream, recorded
+    // after it or after later work on that stream)
+    dvl_status last_event(hipEvent_t* ev) {
+        *ev = nullptr;
+        if (!launched) return DVL_OK;
+        return reader_event(last_stream, false, ev);
+    }
+
+    // the executor's earlier launches are the only users of its buffers:
+    // waiting for the latest one frees them for reuse
     dvl_status wait_idle() {
-        if (launched) DVL_HIP(hipEventSynchronize(last));
+        hipEvent_t ev = nullptr;
+        if (dvl_status st = last_event(&ev)) return st;
+        if (ev) DVL_HIP(hipEventSynchronize(ev));
         return DVL_OK;
     }
 
@@ -820,34 +832,22 @@ struct Executor {
         return DVL_OK;
     }
 
-    // the next ring slot, its previous upload complete, large enough for `need`
-    // bytes on the device (the uploaded block is a prefix of them)
-    dvl_status take_slot(size_t need, Slot** out) {
-        Slot& s = ring[next];
-        next = (next + 1) % kRing;
-        if (s.used) DVL_HIP(hipEventSynchronize(s.ev));
-        if (s.cap < need) {
-            // the new buffers first: on failure the slot keeps its old ones
-            const size_t cap = std::max(need * 2, (size_t)65536);
-            DevBuf d(alloc);
-            if (dvl_status st = d.alloc(cap, "batch descriptors")) return st;
-            char* host = nullptr;
-            if (hipHostMalloc((void**)&host, cap, hipHostMallocDefault) != hipSuccess) {
-                (void)hipGetLastError();
-                return fail(DVL_E_NOMEM, "pinned host allocation of %zu bytes failed", cap);
-            }
-            if (s.dev) {
-                if (dvl_status st = wait_idle()) return st;   // kernels of earlier batches read it
-                alloc.put(s.dev, nullptr);
-                bytes -= s.cap;
-            }
-            if (s.host) (void)hipHostFree(s.host);
-            s.host = host;
-            s.dev = (char*)d.release();
-            s.cap = cap;
-            bytes += cap;
+    // a descriptor block of at least `need` device bytes (the uploaded image
+    // is a prefix of them); the old block is released once the launches that
+    // read it are done
+    dvl_status ensure_block(size_t need) {
+        if (blk_cap >= need) return DVL_OK;
+        const size_t cap = std::max(need * 2, (size_t)65536);
+        DevBuf d(alloc);
+        if (dvl_status st = d.alloc(cap, "batch descriptors")) return st;
+        if (blk) {
+            if (dvl_status st = wait_idle()) return st;
+            alloc.put(blk, nullptr);
+            bytes -= blk_cap;
         }
-        *out = &s;
+        blk = (char*)d.release();
+        blk_cap = cap;
+        bytes += cap;
         return DVL_OK;
     }
 
@@ -866,7 +866,11 @@ struct Executor {
         }
         ev_pending.push_back(ev_pool.back());
         ev_pool.pop_back();
-        *out = ev_pending.back().data();
+        ev_mode.push_back(timing);
+        ev_sel.assign(kPhases + 1, nullptr);
+        for (int p = 0; p <= kPhases; ++p)
+            if (timing == 1 || p == 1 || p == 2) ev_sel[p] = ev_pending.back()[p];
+        *out = ev_sel.data();
         return DVL_OK;
     }
 
@@ -874,35 +878,46 @@ struct Executor {
         for (size_t q = 0; q < P.reqs.size(); ++q) {
             const ReqHost& r = P.reqs[q];
             if (dvl_status st = ensure_ws(q, request_ws_bytes(r.v, r.p.n_bins))) return st;
-            workspace_carve(ws[q].first, r.v->n_tiles, r.v->M, fstore_cells(r.v, r.p.n_bins), &P.rdev[q].ws);
+            workspace_carve(ws[q].first, r.v->n_tiles, r.v->M, r.p.n_bins, fstore_cells(r.v, r.p.n_bins), &P.rdev[q].ws);
         }
         std::vector<CacheBuild> builds;
         if (dvl_status st = decide_cache(P, builds)) return st;
         if (dvl_status st = run_cache_builds(builds, s)) return st;
         if (dvl_status st = cache_wait(P, s)) return st;
-        Slot* slot = nullptr;
-        if (dvl_status st = take_slot(P.device_bytes, &slot)) return st;
-        if (dvl_status st = fill_block(P, slot->host, slot->dev)) return st;
-        DVL_HIP(hipMemcpyAsync(slot->dev, slot->host, P.block_bytes, hipMemcpyHostToDevice, s));
-        DVL_HIP(hipEventRecord(slot->ev, s));
-        slot->used = true;
+        if (dvl_status st = ensure_block(P.device_bytes)) return st;
+        // a launch on another stream than the previous one first waits for it
+        // (it may still read the block and the workspaces)
+        if (launched && s != last_stream) {
+            hipEvent_t prev = nullptr;
+            if (dvl_status st = last_event(&prev)) return st;
+            if (prev) DVL_HIP(hipStreamWaitEvent(s, prev, 0));
+        }
+        img.resize(P.block_bytes);
+        if (dvl_status st = fill_block(P, img.data(), blk)) return st;
+        if (dvl_status st = poke(blk, img.data(), P.block_bytes, s)) return st;
         hipEvent_t* ev = nullptr;
         if (dvl_status st = timing_events(&ev)) return st;
         int paths = 0;
         for (const JobDev& j : P.jobs) paths |= j.idx[0] ? kPathEntries : kPathValues;
         for (const ReqDev& d : P.rdev)
             if (d.ws.fstore) paths |= kPathStoredF;
-        if (dvl_status st = launch_batch(batch_dev(P, slot->dev, paths), P.dtype, P.max_m, P.max_req, n_cu, s, kDescriptorLayout, ev))
+        if (dvl_status st = launch_batch(batch_dev(P, blk, paths), P.dtype, P.max_m, P.max_req, n_cu, s, kDescriptorLayout, ev))
             return st;
-        DVL_HIP(hipEventRecord(last, s));
+        cache_add_readers(P, s);
+        hipEvent_t done = nullptr;
+        if (dvl_status st = reader_event(s, true, &done)) return st;
+        DVL_HIP(hipEventRecord(done, s));
+        last_stream = s;
         launched = true;
-        return cache_mark_readers(P, s);
+        return DVL_OK;
     }
 
     dvl_status kernel_times(double* ms, int32_t* n) {
-        for (auto& set : ev_pending) {
-            DVL_HIP(hipEventSynchronize(set[kPhases]));
-            for (int p = 0; p < kPhases; ++p) {
+        for (size_t i = 0; i < ev_pending.size(); ++i) {
+            auto& set = ev_pending[i];
+            const bool all = ev_mode[i] == 1;
+            DVL_HIP(hipEventSynchronize(set[all ? kPhases : 2]));
+            for (int p = all ? 0 : 1; p < (all ? kPhases : 2); ++p) {
                 float t = 0.0f;
                 DVL_HIP(hipEventElapsedTime(&t, set[p], set[p + 1]));
                 phase_ms[p] += t;
@@ -911,6 +926,7 @@ struct Executor {
             ev_pool.push_back(set);
         }
         ev_pending.clear();
+        ev_mode.clear();
         if (ms)
             for (int p = 0; p < kPhases; ++p) ms[p] = phase_ms[p];
         if (n) *n = timed;
@@ -1006,7 +1022,7 @@ size_t dvl_update_workspace_bytes(int64_t n_cells, int32_t n_fields, int32_t n_b
     if (n_cells < 1 || n_fields < 1 || n_bins < 1) return 0;
     const int64_t cells = (int64_t)kDefaultTileSteps * kStepCells;
     const int64_t T = (n_cells + cells - 1) / cells;
-    return workspace_bytes(T, n_fields, wants_fstore(T, n_bins) ? T * cells : 0);
+    return workspace_bytes(T, n_fields, n_bins, wants_fstore(T, n_bins) ? T * cells : 0);
 }
 
 size_t dvl_request_bytes(const dvl_volume* v, int32_t n_bins) {
@@ -1329,13 +1345,13 @@ dvl_status dvl_update_noalloc(dvl_volume* v, const dvl_params* p, const dvl_bins
     Plan P;
     if (dvl_status st = plan_batch(std::move(reqs), P)) return st;
     const size_t block = al256(P.device_bytes);
-    const size_t need = block + workspace_bytes(v->n_tiles, v->M, 0);
+    const size_t need = block + workspace_bytes(v->n_tiles, v->M, p->n_bins, 0);
     if (need > kScratchBytes)
         return fail(DVL_E_NOMEM, "this update needs %zu bytes of scratch; dvl_update_noalloc has %zu "
                     "(use dvl_update)", need, kScratchBytes);
     char* base = nullptr;
     if (dvl_status st = scratch_address(dev, &base)) return st;
-    workspace_carve(base + block, v->n_tiles, v->M, 0, &P.rdev[0].ws);
+    workspace_carve(base + block, v->n_tiles, v->M, p->n_bins, 0, &P.rdev[0].ws);
     use_existing_cache(P, s);
     if (dvl_status st = cache_wait(P, s)) return st;
     std::vector<char> img(P.block_bytes);
@@ -1615,7 +1631,8 @@ dvl_status dvl_zoom(const dvl_volume* v, uint32_t first, uint32_t last, const dv
 dvl_status dvl_set_timing(dvl_volume* v, int32_t enable) {
     g_err.clear();
     if (dvl_status st = check_volume(v)) return st;
-    v->ex->timing = enable != 0;
+    if (enable < 0 || enable > 2) return fail(DVL_E_INVALID, "timing mode %d (0, 1 or 2)", (int)enable);
+    v->ex->timing = enable;
     return DVL_OK;
 }
 
@@ -1724,7 +1741,8 @@ size_t dvl_executor_bytes(const dvl_executor* ex) {
 dvl_status dvl_executor_set_timing(dvl_executor* ex, int32_t enable) {
     g_err.clear();
     if (!ex) return fail(DVL_E_INVALID, "executor is NULL");
-    reinterpret_cast<Executor*>(ex)->timing = enable != 0;
+    if (enable < 0 || enable > 2) return fail(DVL_E_INVALID, "timing mode %d (0, 1 or 2)", (int)enable);
+    reinterpret_cast<Executor*>(ex)->timing = enable;
     return DVL_OK;
 }
 
@@ -1764,7 +1782,7 @@ dvl_status dvl_graph_create(const dvl_request* reqs, int32_t n_reqs, dvl_graph**
         const ReqHost& r = P.reqs[q];
         if (dvl_status st = w.alloc(request_ws_bytes(r.v, r.p.n_bins), "request workspace")) return st;
         g->ws.push_back(w.release());
-        workspace_carve(g->ws.back(), r.v->n_tiles, r.v->M, fstore_cells(r.v, r.p.n_bins), &P.rdev[q].ws);
+        workspace_carve(g->ws.back(), r.v->n_tiles, r.v->M, r.p.n_bins, fstore_cells(r.v, r.p.n_bins), &P.rdev[q].ws);
     }
     for (int k = 0; k < dvl_graph::kSlots; ++k) {
         DevBuf d(g->alloc);

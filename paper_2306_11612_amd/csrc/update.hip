@@ -42,19 +42,20 @@ namespace dvl {
 
 static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t workspace_bytes(int64_t T, int M, int64_t fcells) {
+size_t workspace_bytes(int64_t T, int M, int W, int64_t fcells) {
     size_t b = 0;
     b += al256((size_t)T * 8);             // local_prefix
     b += al256((size_t)T * 8);             // run_total
     b += al256((size_t)(T + 1) * 8);       // run_base
     b += 2 * al256((size_t)T * 4);         // head/tail bin
     b += 2 * al256((size_t)2 * T * 4);     // rec first/last
+    b += 2 * al256((size_t)W * 4);         // per-bin tile bounds
     b += al256(8 * 8);                     // scalars
     b += al256((size_t)fcells * 4);        // stored importance
     return b;
 }
 
-void workspace_carve(void* base, int64_t T, int M, int64_t fcells, UpdWorkspace* w) {
+void workspace_carve(void* base, int64_t T, int M, int W, int64_t fcells, UpdWorkspace* w) {
     char* p = (char*)base;
     auto take = [&](size_t bytes) { char* q = p; p += al256(bytes); return (void*)q; };
     w->local_prefix = (double*)take((size_t)T * 8);
@@ -64,6 +65,8 @@ void workspace_carve(void* base, int64_t T, int M, int64_t fcells, UpdWorkspace*
     w->tail_bin = (int32_t*)take((size_t)T * 4);
     w->rec_first = (uint32_t*)take((size_t)2 * T * 4);
     w->rec_last = (uint32_t*)take((size_t)2 * T * 4);
+    w->bin_t1 = (int32_t*)take((size_t)W * 4);
+    w->bin_ta = (int32_t*)take((size_t)W * 4);
     w->scal = (double*)take(8 * 8);
     w->fstore = fcells ? (float*)take((size_t)fcells * 4) : nullptr;
 }
@@ -218,6 +221,13 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(BatchDev b) {
 // K3a.  A tile whose pixel interval lies inside one bin puts every cell in
 // that bin: its head record is the whole tile and no cell is read (the
 // projection is hierarchical over tiles).  Other tiles are queued for K3b.
+// Every tile also writes, for the bins its interval reaches, where K4 finds
+// their tiles: with b0(t) = bin of X0(t) (the bin of the tile's first cell)
+// and b1(t) = bin of X1(t) = b0(t + 1), the last tile touching bin b is the
+// t with b0(t) <= b < b1(t) (bin_t1, the last tile: b0 <= b), and the first
+// is the t with b1(t - 1) < b <= b1(t) (bin_ta, the first tile: b <= b1),
+// or the next tile when tile t's last cell ends exactly at bin b's left edge
+// (K4 checks it with the tile's tail bin).  These ranges partition the bins.
 // Each thread classifies kClassifyItems tiles; the workgroup appends its
 // queued tiles with one atomic per projection path (a single counter
 // contended by every wave was the cost of this pass).
@@ -242,6 +252,12 @@ __global__ __launch_bounds__(kClassifyThreads) void k_classify(BatchDev bd) {
             path[r] = q.ws.fstore ? 2 : (j.idx[0] ? 1 : 0);
             const int64_t t = u - q.k3_unit0;
             const TileSpan sp = tile_span(q, j, t);
+            const bool last_tile = t == j.n_tiles - 1;
+            const int W1 = q.W - 1;
+            for (int b = sp.b0, e = last_tile ? W1 : sp.b1 - 1; b <= e; ++b)
+                gstore<int32_t>(q.ws.bin_t1, b, (int32_t)t);
+            for (int b = t == 0 ? 0 : sp.b0 + 1, e = last_tile ? W1 : sp.b1; b <= e; ++b)
+                gstore<int32_t>(q.ws.bin_ta, b, (int32_t)t);
             if (sp.b0 == sp.b1) {
                 const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
                 const int64_t tbase = t * tile_cells;

@@ -30,13 +30,16 @@ struct UpdWorkspace {
     int32_t* tail_bin;    // [T]  bin of the tile's last cell
     uint32_t* rec_first;  // [2][T]  cell range of the tile's head bin, then of its tail bin
     uint32_t* rec_last;   // [2][T]
+    int32_t* bin_t1;      // [W]  last tile whose first cell's bin is <= b (the last tile touching bin b)
+    int32_t* bin_ta;      // [W]  first tile whose pixel interval ends in bin >= b (bin b's first
+                          //      tile, or the one before it when that tile's last cell ends exactly at b)
     double* scal;         // [0] F_tot, [1] degenerate (0/1)
     float* fstore;        // [n_pad] importance of every cell, or NULL (see wants_fstore)
 };
 
-// fcells: cells of the stored importance (0: none)
-size_t workspace_bytes(int64_t n_tiles, int M, int64_t fcells = 0);
-void workspace_carve(void* base, int64_t n_tiles, int M, int64_t fcells, UpdWorkspace* w);
+// n_bins: the request's W; fcells: cells of the stored importance (0: none)
+size_t workspace_bytes(int64_t n_tiles, int M, int n_bins, int64_t fcells = 0);
+void workspace_carve(void* base, int64_t n_tiles, int M, int n_bins, int64_t fcells, UpdWorkspace* w);
 
 // Whether a request stores f in the importance pass for the projection to
 // reuse: worth its 4 B per cell once about a quarter or more of the tiles

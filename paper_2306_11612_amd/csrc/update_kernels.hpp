@@ -375,6 +375,23 @@ __device__ __forceinline__ void vmax_run(const BatchDev& b, const JobDev& j, int
 // cached entries (tables of <= 256 entries) place table (request q, field m)
 // at (q * MT + m) * 256 floats, so that every lookup address is the entry
 // times 4 plus a compile-time offset.
+// n LDS floats dst[i] = value(i), i < n, by the whole workgroup: each thread
+// issues the loads of four of its elements before it stores any, so a round
+// costs one memory latency instead of four (a load-store loop waits for each
+// load alone)
+template <typename F>
+__device__ __forceinline__ void stage_lds(float* dst, int n, F value) {
+    const int tid = thread_x(), nthr = block_dim_x();
+    for (int i0 = tid; i0 < n; i0 += 4 * nthr) {
+        float v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = i0 + k * nthr < n ? value(i0 + k * nthr) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i0 + k * nthr < n) dst[i0 + k * nthr] = v[k];
+    }
+}
+
 template <int MT, bool IDX>
 __device__ __forceinline__ void load_job_tables(const BatchDev& b, const JobDev& j, int ji, int& loaded,
                                                 float* tf_lds) {
@@ -383,14 +400,15 @@ __device__ __forceinline__ void load_job_tables(const BatchDev& b, const JobDev&
         if constexpr (IDX) {
             const int M = uni(fields_of<MT>(j.M)), nq = uni(j.n_req);
             const ReqDev* rq = b.reqs + uni(j.req0);
-            for (int i = thread_x(); i < nq * MT * kIdxTable; i += block_dim_x()) {
+            stage_lds(tf_lds, nq * MT * kIdxTable, [&](int i) {
                 const int q = i / (MT * kIdxTable), m = (i / kIdxTable) % MT, e = i % kIdxTable;
                 float v = 0.0f;
                 if (m < M && e < (int)rq[q].nmax[m] + 1) v = gload<float>(rq[q].tf, rq[q].tf_off[m] + e);
-                tf_lds[i] = v;
-            }
+                return v;
+            });
         } else {
-            for (int i = thread_x(); i < j.tf_total_all; i += block_dim_x()) tf_lds[i] = gload<float>(j.tf_all, i);
+            const float* src = j.tf_all;
+            stage_lds(tf_lds, j.tf_total_all, [&](int i) { return gload<float>(src, i); });
         }
         __syncthreads();
         loaded = ji;
@@ -875,45 +893,59 @@ __device__ __forceinline__ void rescan_walk(const ReqDev& q, const JobDev& j, in
     const uint32_t last_valid = (uint32_t)(tend - 1);
     const int nsteps = (int)((tend - tbase + kStepCells - 1) / kStepCells);
 
-    float run = 0.0f;
+    // The per-step quantities of the sequential walk, for every step at once
+    // (lane s: step s): the running base (the fp32 sum of the earlier steps'
+    // totals, added in step order as the walk would), the bins of the step's
+    // first and last cell, and whether it lies inside one bin.  Lanes past
+    // the last step repeat it.
+    float run_v = 0.0f;
+    int key0_v, key_end_v, fast_v = 0;
+    {
+        const int ls = min(lane, nsteps - 1);
+        for (int k = 0; k < nsteps; ++k) {
+            const float st_k = stage.ex_p[k * kWave].x;   // step k's total (lane 0's Bex slot)
+            if (k < ls) run_v = run_v + st_k;
+        }
+        const int64_t c0 = tbase + (int64_t)ls * kStepCells;
+        const float B63 = stage.ex_p[ls * kWave].x;       // the step total: B of lane 63
+        const float B0 = stage.ex_p[ls * kWave + 1].x;    // B of lane 0: Bex of lane 1
+        const f32x4 e63 = stage.ex_p[ls * kWave + kWave - 1];
+        const float x_first = fminf(fmaf(run_v + fminf(0.0f, B0), scale_f, X0), X1);
+        key0_v = max(0, min((int)floorf(x_first), W1));
+        key_end_v = INT_MAX;
+        if (c0 + kStepCells <= n) {
+            const float x3 = fminf(fmaf(run_v + fminf(e63.x + e63.w, B63), scale_f, X0), X1);
+            const float x4 = (uint32_t)(c0 + kStepCells - 1) == last_valid ? X1
+                                                                          : fminf(fmaf(run_v + B63, scale_f, X0), X1);
+            const int lo3 = max(0, min((int)floorf(x3), W1));
+            key_end_v = max(lo3, min((int)ceilf(x4) - 1, W1));
+            fast_v = key0_v == key_end_v;
+        }
+    }
+
     bool o_valid = false;
     int O = -1, Bh = -1;
     uint32_t O_first = 0;
 
     for (int s = 0; s < nsteps; ++s) {
         const int64_t c0 = tbase + (int64_t)s * kStepCells;
-        const int64_t quad = (c0 >> 2) + lane;
-        const StepPrefix pr = stage.get(s);
-        const float Bex = pr.ex_p.x, p1 = pr.ex_p.y, p2 = pr.ex_p.z, p3 = pr.ex_p.w, B = pr.B;
-        const float stot = readlane(B, kWave - 1);
-        const bool full = c0 + kStepCells <= n;
-
-        // first bin of the step's first cell and last bin of its last cell,
-        // from lanes 0 and 63 alone (the same expressions the per-cell bins
-        // below evaluate): most steps lie inside one bin and stop here
-        const float x_first = fminf(fmaf(run + fminf(0.0f, readlane(B, 0)), scale_f, X0), X1);
-        const int key0 = max(0, min((int)floorf(x_first), W1));
+        const int key0 = readlane(key0_v, s);
         if (s == 0) Bh = key0;
-        int key_end = INT_MAX;
-        if (full) {
-            const float B63 = readlane(B, kWave - 1);
-            const float x3 = fminf(fmaf(run + fminf(readlane(Bex, kWave - 1) + readlane(p3, kWave - 1), B63),
-                                        scale_f, X0), X1);
-            const float x4 = (uint32_t)(c0 + kStepCells - 1) == last_valid ? X1
-                                                                          : fminf(fmaf(run + B63, scale_f, X0), X1);
-            const int lo3 = max(0, min((int)floorf(x3), W1));
-            key_end = max(lo3, min((int)ceilf(x4) - 1, W1));
-        }
-        if (full && key0 == key_end && (!o_valid || key0 == O)) {
+        if (readlane(fast_v, s) && (!o_valid || key0 == O)) {
             // the whole step lies in the open bin
             if (!o_valid) {
                 o_valid = true;
                 O = key0;
                 O_first = (uint32_t)c0;
             }
-            run = run + stot;
             continue;
         }
+        const int key_end = readlane(key_end_v, s);
+        const float run = readlane(run_v, s);
+        const int64_t quad = (c0 >> 2) + lane;
+        const StepPrefix pr = stage.get(s);
+        const float Bex = pr.ex_p.x, p1 = pr.ex_p.y, p2 = pr.ex_p.z, p3 = pr.ex_p.w, B = pr.B;
+        const bool full = c0 + kStepCells <= n;
 
         uint32_t g[4];
         bool valid[4];
@@ -928,7 +960,6 @@ __device__ __forceinline__ void rescan_walk(const ReqDev& q, const JobDev& j, in
         xs[2] = fminf(fmaf(run + fminf(Bex + p2, B), scale_f, X0), X1);
         xs[3] = fminf(fmaf(run + fminf(Bex + p3, B), scale_f, X0), X1);
         xs[4] = fminf(fmaf(run + B, scale_f, X0), X1);
-        run = run + stot;
 
         // pixel bins of each cell: [floor(x1), ceil(x2) - 1], clamped
         int blo[4], bhi[4];
@@ -1025,7 +1056,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
         const int64_t t = u - uni(q.k3_unit0);
         // the tile is rescanned: this request's tables in LDS
         if (qi != loaded) {
-            for (int k = thread_x(); k < q.tf_total; k += kBinThreads) tf_lds[k] = gload<float>(q.tf, k);
+            const float* src = q.tf;
+            stage_lds(tf_lds, q.tf_total, [&](int k) { return gload<float>(src, k); });
             loaded = qi;
         }
         __syncthreads();
@@ -1042,58 +1074,6 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(BatchDev bd) {
 }
 
 // ------------------------------------------------------------------ K4
-
-// First index in [0, T) where `pred` turns false (pred true on a prefix, false
-// after), found by the whole wave: each round the 64 lanes probe 64 evenly
-// spaced points of the remaining range, so three or four rounds of loads
-// replace the ~17 dependent loads of a binary search over 10^5 tiles.
-template <typename Pred>
-__device__ __forceinline__ int64_t wave_partition_point(int64_t T, Pred pred) {
-    const int lane = lane_id();
-    int64_t lo = 0, hi = T;          // the answer lies in [lo, hi]
-    while (lo < hi) {
-        const int64_t step = (hi - lo + kWave - 1) / kWave;
-        const int64_t p = lo + step * lane;
-        const bool t = p < hi && pred(p);
-        const int c = __popcll(__ballot(t));          // lanes 0 .. c-1 hold true
-        if (c == 0) return lo;                       // pred(lo) is false
-        const int64_t new_lo = lo + step * (c - 1) + 1;
-        hi = min(hi, lo + step * c);
-        lo = new_lo;
-    }
-    return lo;
-}
-
-// Two partition points of [0, T) at once (each predicate true on a prefix,
-// false after): lanes 0-31 probe `pa`, lanes 32-63 probe `pb`, 32 evenly
-// spaced points of each remaining range per round, so both searches finish
-// in the rounds one of them would take alone.
-template <typename PA, typename PB>
-__device__ __forceinline__ void wave_partition_points(int64_t T, PA pa, PB pb, int64_t& ra, int64_t& rb) {
-    const int lane = lane_id(), half = lane >> 5, l = lane & 31;
-    int64_t lo[2] = {0, 0}, hi[2] = {T, T};
-    while (lo[0] < hi[0] || lo[1] < hi[1]) {
-        const int64_t step0 = (hi[0] - lo[0] + 31) / 32, step1 = (hi[1] - lo[1] + 31) / 32;
-        const int64_t p = half == 0 ? lo[0] + step0 * l : lo[1] + step1 * l;
-        const bool t = half == 0 ? (p < hi[0] && pa(p)) : (p < hi[1] && pb(p));
-        const uint64_t m = __ballot(t);
-        const int c[2] = {(int)__popcll(m & 0xFFFFFFFFull), (int)__popcll(m >> 32)};
-        const int64_t step[2] = {step0, step1};
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (lo[h] >= hi[h]) continue;
-            if (c[h] == 0) {
-                hi[h] = lo[h];                       // pred(lo) is false
-            } else {
-                const int64_t new_lo = lo[h] + step[h] * (c[h] - 1) + 1;
-                hi[h] = min(hi[h], lo[h] + step[h] * c[h]);
-                lo[h] = new_lo;
-            }
-        }
-    }
-    ra = lo[0];
-    rb = lo[1];
-}
 
 // Field statistics of the sorted cells [first, last], by one wave: the stored
 // values of the partial 256-cell steps at the two ends, the per-step
@@ -1212,10 +1192,10 @@ __global__ __launch_bounds__(256) void k_bin_stats(BatchDev bd) {
     const int32_t* hb = q.ws.head_bin;
     const int32_t* tb = q.ws.tail_bin;
     // tiles touching bin b: t0 = first with tail >= b, t1 = last with head <= b
-    int64_t t0, t1;
-    wave_partition_points(T, [&](int64_t t) { return gload<int32_t>(tb, t) < b; },
-                          [&](int64_t t) { return gload<int32_t>(hb, t) <= b; }, t0, t1);
-    t1 -= 1;
+    // (K3a wrote both per bin; t0 is its candidate or the next tile)
+    const int64_t t1 = uni(gload<int32_t>(q.ws.bin_t1, b));
+    const int64_t ta = uni(gload<int32_t>(q.ws.bin_ta, b));
+    const int64_t t0 = (gload<int32_t>(tb, ta) >= b || ta + 1 >= T) ? ta : ta + 1;
     uint32_t first = 0xFFFFFFFFu, last = 0u;
     bool inside = false;
     if (t0 == t1) {
@@ -1302,7 +1282,7 @@ static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEv
         if (dvl_status st = check_no_static_lds<k_vmax_exact<MT, S, KR, 1>>("k_vmax_exact")) return st;
     }
     auto mark = [&](int i) -> dvl_status {
-        if (ev) DVL_HIP(hipEventRecord(ev[i], s));
+        if (ev && ev[i]) DVL_HIP(hipEventRecord(ev[i], s));
         return DVL_OK;
     };
     const size_t lds1 = (size_t)b.max_job_tf * sizeof(float);

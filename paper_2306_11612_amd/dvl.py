@@ -426,9 +426,10 @@ class Volume:
             return None
         return lo, hi, nt
 
-    def set_timing(self, enable: bool = True):
-        """dvl_set_timing: record per-kernel HIP events on every update."""
-        _check(lib().dvl_set_timing(self.handle, 1 if enable else 0), "dvl_set_timing")
+    def set_timing(self, enable=True):
+        """dvl_set_timing: record per-kernel HIP events on every update
+        (True or 1: every kernel; 2: the importance pass only; False: off)."""
+        _check(lib().dvl_set_timing(self.handle, int(enable)), "dvl_set_timing")
 
     def kernel_times(self):
         """dvl_kernel_times: ({phase: summed ms}, number of updates), then reset."""
@@ -530,8 +531,8 @@ class Executor:
         arr = _request_array(reqs)
         _check(lib().dvl_update_batch(self.handle, arr, len(reqs), _stream_ptr(stream)), "dvl_update_batch")
 
-    def set_timing(self, enable: bool = True):
-        _check(lib().dvl_executor_set_timing(self.handle, 1 if enable else 0), "dvl_executor_set_timing")
+    def set_timing(self, enable=True):
+        _check(lib().dvl_executor_set_timing(self.handle, int(enable)), "dvl_executor_set_timing")
 
     def kernel_times(self):
         ms = np.zeros(5, np.float64)
