@@ -436,8 +436,9 @@ dvl_status dvl_rasterize(const float* y, int32_t n_lines, int32_t n_bins, int32_
  * Per-kernel timing of updates (profiling aid).  With enable = 1, every
  * dvl_update records HIP events on its stream around each of its kernels:
  * phase 0 exact max(V) (VMAX_EXACT only), 1 tile sums of the importance,
- * 2 carry scan, 3 projection (tile classification and rescan: bin cell
- * ranges), 4 bin statistics (mean, min, max, height per bin).  With
+ * 2 carry scan and tile classification (one kernel), 3 rescan of the tiles
+ * holding a bin edge (bin cell ranges), 4 bin statistics (mean, min, max,
+ * height per bin).  With
  * enable = 2 only the two events around phase 1 (the importance pass, the
  * dominant kernel) are recorded; the other phases read 0.  0 disables;
  * other values return DVL_E_INVALID.

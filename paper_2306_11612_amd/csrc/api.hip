@@ -527,7 +527,7 @@ static dvl_status plan_batch(std::vector<ReqHost>&& reqs, Plan& P) {
         d.f_total = r.out.f_total;
         d.vmax_used = r.out.vmax_used;
     }
-    P.off_jobs = 256;
+    P.off_jobs = 256 + al256(P.rdev.size() * sizeof(uint32_t));   // counters, then carry flags
     P.off_reqs = P.off_jobs + al256(P.jobs.size() * sizeof(JobDev));
     P.off_vmax = P.off_reqs + al256(P.rdev.size() * sizeof(ReqDev));
     P.off_tf = P.off_vmax + al256(P.rdev.size() * sizeof(float));
@@ -557,7 +557,7 @@ static dvl_status fill_block(Plan& P, char* h, char* d) {
         P.rdev[q].vmax_dev = (float*)(d + P.off_vmax) + q;
     }
     for (auto& j : P.jobs) j.tf_all = (const float*)(d + P.off_tf) + P.reqs[j.req0].tf_pos;
-    memset(h, 0, P.off_jobs);   // rescan counters start at 0
+    memset(h, 0, P.off_jobs);   // rescan counters and carry flags start at 0
     memcpy(h + P.off_jobs, P.jobs.data(), P.jobs.size() * sizeof(JobDev));
     memcpy(h + P.off_reqs, P.rdev.data(), P.rdev.size() * sizeof(ReqDev));
     return DVL_OK;
@@ -733,6 +733,7 @@ static BatchDev batch_dev(const Plan& P, char* d, int paths) {
     b.jobs = (const JobDev*)(d + P.off_jobs);
     b.reqs = (const ReqDev*)(d + P.off_reqs);
     b.rescan_count = (uint32_t*)d;
+    b.carry_ready = (uint32_t*)(d + 256);
     b.rescan_queue = (uint64_t*)(d + P.off_queue);
     b.n_jobs = (int)P.jobs.size();
     b.n_reqs = (int)P.rdev.size();

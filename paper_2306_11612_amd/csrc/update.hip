@@ -7,9 +7,11 @@
 //                     cell for every request of its job (one read of the
 //                     cells); fp64 sum of f per tile; each wave owns a run of
 //                     consecutive tiles and records their prefix inside it
-//   K2 k_carry        per request: exclusive scan of the run totals (Eq. 4
-//                     across runs; fp64 or compensated fp32), made monotone
-//   K3a k_classify    per (request, tile), one lane each: if the tile's pixel
+//   K2 + K3a k_carry_classify (one kernel)
+//                     K2, per request: exclusive scan of the run totals (Eq. 4
+//                     across runs; fp64 or compensated fp32), made monotone;
+//                     K3a, per (request, tile), one lane each, once the
+//                     request's carry is published: if the tile's pixel
 //                     interval lies inside one bin, the whole tile is that
 //                     bin's part; otherwise the tile is queued
 //   K3b k_bin         per queued tile: recompute f, monotone in-tile prefix,
@@ -207,8 +209,10 @@ __device__ void carry_scan(const ReqDev& q, int64_t T, int64_t n_cells) {
     }
 }
 
-__global__ __launch_bounds__(kCarryThreads) void k_carry(BatchDev b) {
-    const ReqDev& q = b.reqs[block_x()];
+// The carry of request q, in the request's scan arithmetic (the whole
+// workgroup; writes run_base and the scalars).
+__device__ void scan_request(const BatchDev& b, int q_index) {
+    const ReqDev& q = b.reqs[q_index];
     const JobDev& j = b.jobs[q.job];
     if (q.scan_mode == DVL_SCAN_KAHAN_FP32)
         carry_scan<AccKahan32>(q, j.n_runs, j.n);
@@ -228,60 +232,93 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry(BatchDev b) {
 // is the t with b1(t - 1) < b <= b1(t) (bin_ta, the first tile: b <= b1),
 // or the next tile when tile t's last cell ends exactly at bin b's left edge
 // (K4 checks it with the tile's tail bin).  These ranges partition the bins.
-// Each thread classifies kClassifyItems tiles; the workgroup appends its
-// queued tiles with one atomic per projection path (a single counter
-// contended by every wave was the cost of this pass).
-constexpr int kClassifyItems = 4;
-constexpr int kClassifyThreads = 256;
+// Each thread classifies one tile; the workgroup appends its queued tiles
+// with one atomic per projection path (a single counter contended by every
+// wave was the cost of this pass).
+//
+// K2 and K3a run as one kernel: workgroup q < n_reqs scans request q's run
+// totals and then publishes it (agent-scope release of carry_ready[q]);
+// the other workgroups classify 1024 tiles each once the carries of their
+// requests are published (agent-scope acquire), which saves a launch and
+// its queue drain between the two.  The wait is bounded: a workgroup that
+// has not seen the flag after kCarryWaitSpins polls scans the request
+// itself (the same code on the same inputs writes the same bits), so the
+// kernel finishes whatever the order in which its workgroups run.
+constexpr int kClassifyThreads = kCarryThreads;
+constexpr int kCarryWaitSpins = 1 << 15;
 
-__global__ __launch_bounds__(kClassifyThreads) void k_classify(BatchDev bd) {
+__device__ __forceinline__ void await_carry(const BatchDev& b, int q) {
+    __shared__ int ready;
+    if (thread_x() == 0) {
+        // polls are relaxed (an acquiring load invalidates the L2 each time,
+        // which slowed the scan it waits for); one acquire fence follows
+        uint32_t* flag = b.carry_ready + q;
+        int spins = 0;
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u && spins < kCarryWaitSpins) {
+            __builtin_amdgcn_s_sleep(4);
+            ++spins;
+        }
+        ready = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (!ready) scan_request(b, q);
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kClassifyThreads) void k_carry_classify(BatchDev bd) {
+    if (block_x() < bd.n_reqs) {
+        scan_request(bd, block_x());
+        __syncthreads();
+        if (thread_x() == 0) {
+            __threadfence();
+            __hip_atomic_store(bd.carry_ready + block_x(), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
     __shared__ uint32_t wcount[3][kClassifyThreads / kWave];
     __shared__ uint32_t wbase[3];
     const int lane = lane_id(), w = thread_x() / kWave;
-    const int64_t u0 = (int64_t)block_x() * kClassifyThreads * kClassifyItems;
-    bool need[kClassifyItems];
-    int path[kClassifyItems];
-#pragma unroll
-    for (int r = 0; r < kClassifyItems; ++r) {
-        const int64_t u = u0 + (int64_t)r * kClassifyThreads + thread_x();
-        need[r] = false;
-        path[r] = 0;
-        if (u < bd.k3_units) {
-            const ReqDev& q = bd.reqs[find_req_k3(bd, u)];
-            const JobDev& j = bd.jobs[q.job];
-            path[r] = q.ws.fstore ? 2 : (j.idx[0] ? 1 : 0);
-            const int64_t t = u - q.k3_unit0;
-            const TileSpan sp = tile_span(q, j, t);
-            const bool last_tile = t == j.n_tiles - 1;
-            const int W1 = q.W - 1;
-            for (int b = sp.b0, e = last_tile ? W1 : sp.b1 - 1; b <= e; ++b)
-                gstore<int32_t>(q.ws.bin_t1, b, (int32_t)t);
-            for (int b = t == 0 ? 0 : sp.b0 + 1, e = last_tile ? W1 : sp.b1; b <= e; ++b)
-                gstore<int32_t>(q.ws.bin_ta, b, (int32_t)t);
-            if (sp.b0 == sp.b1) {
-                const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
-                const int64_t tbase = t * tile_cells;
-                gstore<uint32_t>(q.ws.rec_first, t, (uint32_t)tbase);
-                gstore<uint32_t>(q.ws.rec_last, t, (uint32_t)(min(tbase + tile_cells, j.n) - 1));
-                gstore<int32_t>(q.ws.head_bin, t, sp.b0);
-                gstore<int32_t>(q.ws.tail_bin, t, sp.b0);
-            } else {
-                need[r] = true;
-            }
+    const int64_t u0 = (int64_t)(block_x() - bd.n_reqs) * kClassifyThreads;
+    // the requests of this workgroup's tiles: their carries first
+    {
+        const int qa = find_req_k3(bd, u0);
+        const int qb = find_req_k3(bd, min(u0 + kClassifyThreads, bd.k3_units) - 1);
+        for (int q = qa; q <= qb; ++q) await_carry(bd, q);
+    }
+    const int64_t u = u0 + thread_x();
+    bool need = false;
+    int path = 0;
+    if (u < bd.k3_units) {
+        const ReqDev& q = bd.reqs[find_req_k3(bd, u)];
+        const JobDev& j = bd.jobs[q.job];
+        path = q.ws.fstore ? 2 : (j.idx[0] ? 1 : 0);
+        const int64_t t = u - q.k3_unit0;
+        const TileSpan sp = tile_span(q, j, t);
+        const bool last_tile = t == j.n_tiles - 1;
+        const int W1 = q.W - 1;
+        for (int b = sp.b0, e = last_tile ? W1 : sp.b1 - 1; b <= e; ++b)
+            gstore<int32_t>(q.ws.bin_t1, b, (int32_t)t);
+        for (int b = t == 0 ? 0 : sp.b0 + 1, e = last_tile ? W1 : sp.b1; b <= e; ++b)
+            gstore<int32_t>(q.ws.bin_ta, b, (int32_t)t);
+        if (sp.b0 == sp.b1) {
+            const int64_t tile_cells = (int64_t)j.tile_steps * kStepCells;
+            const int64_t tbase = t * tile_cells;
+            gstore<uint32_t>(q.ws.rec_first, t, (uint32_t)tbase);
+            gstore<uint32_t>(q.ws.rec_last, t, (uint32_t)(min(tbase + tile_cells, j.n) - 1));
+            gstore<int32_t>(q.ws.head_bin, t, sp.b0);
+            gstore<int32_t>(q.ws.tail_bin, t, sp.b0);
+        } else {
+            need = true;
         }
     }
     // per path: the wave's queued tiles, then one atomic for the workgroup
-    uint32_t mine_before[3][kClassifyItems];
+    uint32_t mine_before[3];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int r = 0; r < kClassifyItems; ++r) {
-            const uint64_t mask = __ballot(need[r] && path[r] == p);
-            mine_before[p][r] = c + (uint32_t)__popcll(mask & lanemask_lt());
-            c += (uint32_t)__popcll(mask);
-        }
-        if (lane == 0) wcount[p][w] = c;
+        const uint64_t mask = __ballot(need && path == p);
+        mine_before[p] = (uint32_t)__popcll(mask & lanemask_lt());
+        if (lane == 0) wcount[p][w] = (uint32_t)__popcll(mask);
     }
     __syncthreads();
     if (thread_x() < 3) {
@@ -291,15 +328,10 @@ __global__ __launch_bounds__(kClassifyThreads) void k_classify(BatchDev bd) {
         wbase[p] = tot ? atomicAdd(bd.rescan_count + p, tot) : 0u;
     }
     __syncthreads();
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        uint32_t base = wbase[p];
-        for (int k = 0; k < w; ++k) base += wcount[p][k];
-#pragma unroll
-        for (int r = 0; r < kClassifyItems; ++r)
-            if (need[r] && path[r] == p)
-                gstore<uint64_t>(bd.rescan_queue, p * bd.k3_units + base + mine_before[p][r],
-                                 (uint64_t)(u0 + (int64_t)r * kClassifyThreads + thread_x()));
+    if (need) {
+        uint32_t base = wbase[path];
+        for (int k = 0; k < w; ++k) base += wcount[path][k];
+        gstore<uint64_t>(bd.rescan_queue, path * bd.k3_units + base + mine_before[path], (uint64_t)u);
     }
 }
 
@@ -460,16 +492,9 @@ dvl_status launch_build_index(int64_t n_pad, int dtype, const void* field, float
 
 // ------------------------------------------------------------------ launchers
 
-dvl_status launch_carry(const BatchDev& b, hipStream_t s) {
-    hipLaunchKernelGGL(k_carry, dim3((unsigned)b.n_reqs), dim3(kCarryThreads), 0, s, b);
-    DVL_HIP(hipGetLastError());
-    return DVL_OK;
-}
-
-dvl_status launch_classify(const BatchDev& b, hipStream_t s) {
-    const int64_t per_block = (int64_t)kClassifyThreads * kClassifyItems;
-    const unsigned g = (unsigned)std::max<int64_t>(1, (b.k3_units + per_block - 1) / per_block);
-    hipLaunchKernelGGL(k_classify, dim3(g), dim3(kClassifyThreads), 0, s, b);
+dvl_status launch_carry_classify(const BatchDev& b, hipStream_t s) {
+    const int64_t blocks = (int64_t)b.n_reqs + (b.k3_units + kClassifyThreads - 1) / kClassifyThreads;
+    hipLaunchKernelGGL(k_carry_classify, dim3((unsigned)blocks), dim3(kClassifyThreads), 0, s, b);
     DVL_HIP(hipGetLastError());
     return DVL_OK;
 }

@@ -15,7 +15,7 @@ constexpr int kCellsPerLane = 4;                 // one 4-vector per field per s
 constexpr int kStepCells = kWave * kCellsPerLane;    // 256 cells per wave step
 constexpr int kDefaultTileSteps = 16;            // 4096-cell tiles unless tuned
 constexpr int kMaxReqPerJob = 8;
-constexpr int kPhases = 5;                       // exact vmax, tile sums, carry, bin edges, bin statistics
+constexpr int kPhases = 5;                       // exact vmax, tile sums, carry + classification, rescan, bin statistics
 constexpr int kPathValues = 1;                   // jobs that read the field values
 constexpr int kPathEntries = 2;                  // jobs that read cached TF entries
 constexpr int kPathStoredF = 4;                  // requests whose projection reads stored f
@@ -109,6 +109,7 @@ struct BatchDev {
     const JobDev* jobs;
     const ReqDev* reqs;
     uint32_t* rescan_count;   // [3] tiles queued for a rescan per projection path (0 when uploaded)
+    uint32_t* carry_ready;    // [n_reqs] set once a request's carry is published (0 when uploaded)
     uint64_t* rescan_queue;   // [3][k3_units] projection units of the queued tiles, per path
     int n_jobs;
     int n_reqs;

@@ -1256,8 +1256,7 @@ __global__ __launch_bounds__(256) void k_bin_stats(BatchDev bd) {
 // ------------------------------------------------------------------ launcher
 
 // launchers of the kernels that do not depend on the storage type (update.hip)
-dvl_status launch_carry(const BatchDev& b, hipStream_t s);
-dvl_status launch_classify(const BatchDev& b, hipStream_t s);
+dvl_status launch_carry_classify(const BatchDev& b, hipStream_t s);
 
 // The cached-entry importance kernels address their tables from LDS address
 // 0 (the start of the dynamic LDS array): they must hold no static LDS.
@@ -1309,9 +1308,8 @@ static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEv
         DVL_HIP(hipGetLastError());
     }
     if (dvl_status st = mark(2)) return st;
-    if (dvl_status st = launch_carry(b, s)) return st;
+    if (dvl_status st = launch_carry_classify(b, s)) return st;
     if (dvl_status st = mark(3)) return st;
-    if (dvl_status st = launch_classify(b, s)) return st;
     const size_t lds3 = (size_t)((b.max_req_tf + 3) & ~3) * sizeof(float) + (size_t)b.max_tile_steps * kStageBytesPerStep;
     const unsigned g3 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.k3_units, (int64_t)n_cu * 16));
     if (b.paths & kPathValues) {
