@@ -816,7 +816,7 @@ constexpr size_t kStageBytesPerStep = (size_t)kWave * sizeof(f32x4);
 // Phase 1 of the rescan, for the steps s = w, w + kBinWaves, ... of tile t
 // taken by wave w: f of every cell again (from values, cached entries or the
 // stored f, bit for bit as in K1; 1 when the total importance is 0) and the
-// step's monotone prefix, into LDS.  Loads run one step ahead.
+// step's monotone prefix, into LDS.
 template <int MT, typename S, typename D>
 __device__ __forceinline__ void rescan_stage(const ReqDev& q, const JobDev& j, int64_t t, const float* tf_lds,
                                              Stage stage) {
@@ -839,12 +839,7 @@ __device__ __forceinline__ void rescan_stage(const ReqDev& q, const JobDev& j, i
     int off[MT];
     table_offsets<MT>(q, M, off);
     if (w >= nsteps) return;
-    // two of this wave's steps in flight
-    D cur, nxt;
-    const int s1 = min(w + kBinWaves, nsteps - 1);
-    cur.load(view, M, w, gload<uint32_t>(view.lcode, w));
-    nxt.load(view, M, s1, gload<uint32_t>(view.lcode, s1));
-    for (int s = w; s < nsteps; s += kBinWaves) {
+    auto process = [&](const D& cur, int s) {
         const int64_t quad = ((tbase + (int64_t)s * kStepCells) >> 2) + lane;
         float f[4];
 #pragma unroll
@@ -868,9 +863,50 @@ __device__ __forceinline__ void rescan_stage(const ReqDev& q, const JobDev& j, i
         sp.ex_p.w = p3;
         sp.B = B;
         stage.put(s, sp);
-        cur = nxt;
-        const int sn = min(s + 2 * kBinWaves, nsteps - 1);
-        nxt.load(view, M, sn, gload<uint32_t>(view.lcode, sn));
+    };
+    if constexpr (!std::is_same<D, StepData<MT, S>>::value) {
+        // cached entries or stored f (a few registers per step): the level
+        // codes of all of this wave's steps first (uniform: scalar registers;
+        // a lane's level load address depends on its code), then the steps
+        // two at a time, loaded together and then processed (two keep the
+        // rescan within 64 VGPRs, eight waves per SIMD)
+        constexpr int kAhead = 2;
+        constexpr int kMaxPer = (kMaxTileSteps + kBinWaves - 1) / kBinWaves;
+        const int cnt = (nsteps - w + kBinWaves - 1) / kBinWaves;
+        uint32_t code[kMaxPer];
+#pragma unroll
+        for (int k = 0; k < kMaxPer; ++k) {
+            code[k] = 0u;
+            if constexpr (std::is_same<D, StepIdx<MT>>::value)
+                if (k < cnt) code[k] = uni(gload<uint32_t>(view.lcode, w + k * kBinWaves));
+        }
+#pragma unroll
+        for (int k0 = 0; k0 < kMaxPer; k0 += kAhead) {
+            if (k0 >= cnt) break;
+            D buf[kAhead];
+#pragma unroll
+            for (int k = 0; k < kAhead; ++k)
+                if (k0 + k < cnt) buf[k].load(view, M, w + (k0 + k) * kBinWaves, code[k0 + k]);
+#pragma unroll
+            for (int k = 0; k < kAhead; ++k)
+                if (k0 + k < cnt) process(buf[k], w + (k0 + k) * kBinWaves);
+        }
+    } else {
+        // values: two steps in flight in buffers that take turns (no loaded
+        // register is copied, so each wait is for the older step only)
+        D A, B;
+        A.load(view, M, w, gload<uint32_t>(view.lcode, w));
+        const int s1 = min(w + kBinWaves, nsteps - 1);
+        B.load(view, M, s1, gload<uint32_t>(view.lcode, s1));
+        for (int s = w; s < nsteps; s += 2 * kBinWaves) {
+            process(A, s);
+            const int s2 = min(s + 2 * kBinWaves, nsteps - 1);
+            A.load(view, M, s2, gload<uint32_t>(view.lcode, s2));
+            if (s + kBinWaves >= nsteps) break;
+            process(B, s + kBinWaves);
+            const int s3 = min(s + 3 * kBinWaves, nsteps - 1);
+            B.load(view, M, s3, gload<uint32_t>(view.lcode, s3));
+        }
     }
 }
 
