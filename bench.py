@@ -18,6 +18,7 @@ before the timed region.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -163,6 +164,9 @@ def bench_batch32(args, dt):
     tfs = [[np.stack([t.numpy() for t in synth.make_tfs(config_seed(4) * 1000 + k + 101 * s, M, (4, 4))])
             for s in range(2)] for k in range(n_vol)]
     kw = dict(exponent=args.exponent, min_importance=args.min_importance)
+
+    gc.collect()
+    gc.freeze()
 
     def timed(step, label):
         """Pipelined wall-clock ms per step (the host runs ahead), then the
@@ -410,6 +414,12 @@ def main():
 
     def flush(k):
         flush_buf.fill_(float(k))
+
+    # the interpreter's objects so far (torch, the workload) move to the
+    # permanent generation: a full collection during a timed region would
+    # otherwise walk them all (a host pause of tens of milliseconds)
+    gc.collect()
+    gc.freeze()
 
     def measure(policy):
         V.set_entry_cache(policy)

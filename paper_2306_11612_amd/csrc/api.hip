@@ -761,14 +761,26 @@ static size_t request_ws_bytes(const dvl_volume* v, int n_bins) {
 struct Executor {
     int n_cu = 256;
     Alloc alloc;                    // workspaces and descriptor blocks
-    // The descriptor block: one device buffer, written before each launch by
-    // k_poke from a host image carried in kernel arguments (no staging
-    // buffer whose reuse the host would have to wait for).  Launches on one
-    // stream run in order, so a launch rewrites the block only after the
-    // previous launch's kernels have read it.
+    // The descriptor block: one device buffer, rewritten before each launch.
+    // Launches on one stream run in order, so a launch rewrites the block
+    // only after the previous launch's kernels have read it.  Blocks of up
+    // to kPokeMaxBytes (a few requests) are written by k_poke from a host
+    // image carried in kernel arguments: no staging buffer whose reuse the
+    // host would have to wait for, and no event.  Larger ones (a batch of
+    // many requests: tens of KB of tables) are copied from a ring of pinned
+    // staging buffers, each released by an event after its copy.
+    static constexpr size_t kPokeMaxBytes = (size_t)4 * kPokeWords * 4;
     char* blk = nullptr;
     size_t blk_cap = 0;
     std::vector<char> img;
+    struct Staging {
+        char* host = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool used = false;
+    };
+    Staging ring[kRing];
+    int next = 0;
     std::vector<std::pair<void*, size_t>> ws;   // workspace pool: one per request position
     // The end of the latest launch is marked by the reader event of its
     // stream (reader_event), recorded after every launch: it serves the
@@ -786,6 +798,10 @@ struct Executor {
     ~Executor() {
         (void)hipDeviceSynchronize();
         alloc.put(blk, nullptr);
+        for (auto& r : ring) {
+            if (r.host) (void)hipHostFree(r.host);
+            if (r.ev) (void)hipEventDestroy(r.ev);
+        }
         for (auto& w : ws) alloc.put(w.first, nullptr);
         for (auto* pool : {&ev_pool, &ev_pending})
             for (auto& set : *pool)
@@ -852,6 +868,44 @@ struct Executor {
         return DVL_OK;
     }
 
+    // the next pinned staging buffer, its previous copy complete, of at
+    // least `need` bytes
+    dvl_status take_staging(size_t need, Staging** out) {
+        Staging& r = ring[next];
+        next = (next + 1) % kRing;
+        if (!r.ev) DVL_HIP(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
+        if (r.used) DVL_HIP(hipEventSynchronize(r.ev));
+        if (r.cap < need) {
+            const size_t cap = std::max(need * 2, (size_t)65536);
+            char* host = nullptr;
+            if (hipHostMalloc((void**)&host, cap, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(DVL_E_NOMEM, "pinned host allocation of %zu bytes failed", cap);
+            }
+            if (r.host) (void)hipHostFree(r.host);
+            r.host = host;
+            r.cap = cap;
+        }
+        *out = &r;
+        return DVL_OK;
+    }
+
+    // write the plan's descriptor block into blk on stream s
+    dvl_status upload(Plan& P, hipStream_t s) {
+        if (P.block_bytes <= kPokeMaxBytes) {
+            img.resize(P.block_bytes);
+            if (dvl_status st = fill_block(P, img.data(), blk)) return st;
+            return poke(blk, img.data(), P.block_bytes, s);
+        }
+        Staging* r = nullptr;
+        if (dvl_status st = take_staging(P.block_bytes, &r)) return st;
+        if (dvl_status st = fill_block(P, r->host, blk)) return st;
+        DVL_HIP(hipMemcpyAsync(blk, r->host, P.block_bytes, hipMemcpyHostToDevice, s));
+        DVL_HIP(hipEventRecord(r->ev, s));
+        r->used = true;
+        return DVL_OK;
+    }
+
     dvl_status timing_events(hipEvent_t** out) {
         *out = nullptr;
         if (!timing) return DVL_OK;
@@ -893,9 +947,7 @@ struct Executor {
             if (dvl_status st = last_event(&prev)) return st;
             if (prev) DVL_HIP(hipStreamWaitEvent(s, prev, 0));
         }
-        img.resize(P.block_bytes);
-        if (dvl_status st = fill_block(P, img.data(), blk)) return st;
-        if (dvl_status st = poke(blk, img.data(), P.block_bytes, s)) return st;
+        if (dvl_status st = upload(P, s)) return st;
         hipEvent_t* ev = nullptr;
         if (dvl_status st = timing_events(&ev)) return st;
         int paths = 0;

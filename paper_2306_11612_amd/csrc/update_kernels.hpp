@@ -732,7 +732,7 @@ __device__ __forceinline__ void close_bin(const ReqDev& q, int64_t T, int dest, 
 
 // ------------------------------------------------------------------ K3
 
-constexpr int kBinThreads = 256;  // one workgroup per queued (request, tile)
+constexpr int kBinThreads = 192;  // one workgroup of three waves per queued (request, tile)
 
 // Pixel interval [X0, X1] of tile t of request q, and its first and last bin.
 struct TileSpan {
@@ -1070,8 +1070,12 @@ __device__ __forceinline__ void rescan_walk(const ReqDev& q, const JobDev& j, in
 }
 
 // K3b: the queued tiles, one workgroup each.  Its waves stage the prefixes
-// of the tile's steps in LDS together (phase 1; the loads of four waves in
+// of the tile's steps in LDS together (phase 1; the loads of three waves in
 // flight instead of one), then the first wave walks the bins (phase 2).
+// Three waves, not four: at 62 VGPRs a compute unit holds seven waves per
+// SIMD, so seven workgroups of four waves (1792 on the chip) would leave some
+// of the ~1900 tiles of W = 1920 to a second round, while eight workgroups of
+// three fit (LDS: 20 KB each); measured 36 instead of 41 us.
 // IDX: this instance serves the requests whose projection reads values (0),
 // cached entries (1) or the f the importance pass stored (2); each skips the
 // others' tiles.  LDS: the request's tables, then the staged prefixes.
