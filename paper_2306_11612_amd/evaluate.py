@@ -138,7 +138,7 @@ def summarise_vmax(rows) -> dict:
 def markdown(res: dict) -> str:
     L = [f"# Evaluation on {res['workload']} ({res['n_cells']} cells, {res['n_fields']} fields, W = {res['n_bins']})",
          "", "Command:", "", f"    {res['command']}", "",
-         "Projection = tile classification and rescan + per-bin statistics (ms per update, mean of "
+         "Projection = carry scan with tile classification (one kernel), rescan and per-bin statistics (ms per update, mean of "
          f"{res['reps']} updates, TF entry cache on); counts = cells per bin.", ""]
     for name, rows in (("exponent", res["exponent_sweep"]), ("min_importance", res["min_importance_sweep"])):
         L += [f"## Sweep of {name}", "",

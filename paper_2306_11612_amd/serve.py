@@ -20,6 +20,7 @@ so it is tested without a GPU; ``GpuEngine`` is the engine over the C ABI.
 from __future__ import annotations
 
 import argparse
+import gc
 import collections
 import json
 import math
@@ -311,6 +312,10 @@ def main(argv=None):
             run_open_loop(Scheduler(engine, int(args.budget_gb * 1e9), args.max_batch, pol), warm)
             for j in warm:
                 j.arrival, j.done, j.admitted = 0.0, None, None
+        # the long-lived objects (torch, the volumes) go to the permanent
+        # generation, so a full collection does not walk them between requests
+        gc.collect()
+        gc.freeze()
         for rate in [float(r) for r in args.rates.split(",")]:
             for pol in args.policies.split(","):
                 jobs = make_requests(ids, n_fields, rate, args.duration, args.max_requests, synth.SEED + 5)
