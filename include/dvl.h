@@ -257,10 +257,10 @@ dvl_status dvl_update(dvl_volume* v, const dvl_params* p, const dvl_bins* out, v
  * Its descriptors and workspace live in one fixed device scratch array of
  * dvl_update_noalloc_max_bytes() bytes (64 MiB) per device, held from the
  * first call on that device until the process ends; the descriptors are
- * written by kernels (no memcpy, no memset).  A volume fits when 72 bytes
- * per 4096-cell tile plus about 24 KB stay within it (about 3.8e9 cells,
- * whatever the field count); larger ones get DVL_E_NOMEM with a message and
- * nothing is enqueued.  It never stores f for the projection and never
+ * written by kernels (no memcpy, no memset).  An update fits when 72 bytes
+ * per 4096-cell tile, 8 bytes per bin and about 24 KB stay within it (about
+ * 3.8e9 cells at W = 1920, whatever the field count); larger ones get
+ * DVL_E_NOMEM with a message and nothing is enqueued.  It never stores f for the projection and never
  * builds the TF entry cache: it reads the cache only when the cache already
  * holds this update's windows and the volume was updated on this stream
  * before.  Every call on a device shares that device's scratch, which keeps
@@ -449,6 +449,18 @@ dvl_status dvl_rasterize(const float* y, int32_t n_lines, int32_t n_bins, int32_
  * ------------------------------------------------------------------- */
 dvl_status dvl_set_timing(dvl_volume* v, int32_t enable);
 dvl_status dvl_kernel_times(dvl_volume* v, double* ms, int32_t* n_updates);
+
+/* ---------------------------------------------------------------------
+ * Test hook of the carry hand-off (process-wide; read when a launch is
+ * enqueued or a batch is captured).  The carry scan of Eq. 4 across runs
+ * and the classification of the tiles (section Projecting Cells to 1D) run
+ * as one kernel: each classifying workgroup polls a flag the request's scan
+ * workgroup sets, and computes the carry itself after `polls` unanswered
+ * polls (default 32768), writing the same values.  polls = 0 makes every
+ * classifying workgroup take that path, so tests can check that it gives
+ * the same bits.  DVL_E_INVALID for polls < 0.
+ * ------------------------------------------------------------------- */
+dvl_status dvl_set_carry_wait(int32_t polls);
 
 int64_t dvl_num_cells(const dvl_volume* v);
 int32_t dvl_num_fields(const dvl_volume* v);

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <string>
@@ -725,6 +726,10 @@ static dvl_status cache_mark_readers(const Plan& P, hipStream_t s) {
     return DVL_OK;
 }
 
+// polls of a request's carry flag before a classifying workgroup computes the
+// carry itself (dvl_set_carry_wait)
+static std::atomic<int> g_carry_wait_polls{kCarryWaitPolls};
+
 // `paths`: importance-pass variants to launch (a captured graph takes both,
 // since its jobs choose at every launch)
 static BatchDev batch_dev(const Plan& P, char* d, int paths) {
@@ -745,6 +750,7 @@ static BatchDev batch_dev(const Plan& P, char* d, int paths) {
     b.max_job_tf = P.max_job_tf;
     b.max_req_job = P.max_req;
     b.max_tile_steps = 8;
+    b.carry_wait_polls = g_carry_wait_polls.load(std::memory_order_relaxed);
     for (const JobDev& j : P.jobs) b.max_tile_steps = std::max(b.max_tile_steps, j.tile_steps);
     return b;
 }
@@ -1430,6 +1436,13 @@ dvl_status dvl_update_noalloc(dvl_volume* v, const dvl_params* p, const dvl_bins
 }
 
 size_t dvl_update_noalloc_max_bytes(void) { return kScratchBytes; }
+
+dvl_status dvl_set_carry_wait(int32_t polls) {
+    g_err.clear();
+    if (polls < 0) return fail(DVL_E_INVALID, "polls %d < 0", (int)polls);
+    g_carry_wait_polls.store(polls, std::memory_order_relaxed);
+    return DVL_OK;
+}
 
 dvl_status dvl_read_bins(const dvl_volume* v, const dvl_bins* b, int32_t W, void* stream, uint32_t* count,
                          uint32_t* first, uint32_t* last, float* mean, float* vmin, float* vmax, float* y,

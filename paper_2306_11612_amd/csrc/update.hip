@@ -241,11 +241,10 @@ __device__ void scan_request(const BatchDev& b, int q_index) {
 // the other workgroups classify 1024 tiles each once the carries of their
 // requests are published (agent-scope acquire), which saves a launch and
 // its queue drain between the two.  The wait is bounded: a workgroup that
-// has not seen the flag after kCarryWaitSpins polls scans the request
+// has not seen the flag after b.carry_wait_polls polls scans the request
 // itself (the same code on the same inputs writes the same bits), so the
 // kernel finishes whatever the order in which its workgroups run.
 constexpr int kClassifyThreads = kCarryThreads;
-constexpr int kCarryWaitSpins = 1 << 15;
 
 __device__ __forceinline__ void await_carry(const BatchDev& b, int q) {
     __shared__ int ready;
@@ -254,7 +253,7 @@ __device__ __forceinline__ void await_carry(const BatchDev& b, int q) {
         // which slowed the scan it waits for); one acquire fence follows
         uint32_t* flag = b.carry_ready + q;
         int spins = 0;
-        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u && spins < kCarryWaitSpins) {
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u && spins < b.carry_wait_polls) {
             __builtin_amdgcn_s_sleep(4);
             ++spins;
         }

@@ -122,7 +122,12 @@ struct BatchDev {
     int max_job_tf;           // largest job table block (floats): LDS of the importance pass
     int max_req_job;          // most requests in one job
     int max_tile_steps;       // largest tile (256-cell steps) of the batch's volumes
+    int carry_wait_polls;     // bounded wait of the classification for a published carry
 };
+
+// Polls of a request's carry flag before a classifying workgroup computes the
+// carry itself (the default; dvl_set_carry_wait changes it for tests).
+constexpr int kCarryWaitPolls = 1 << 15;
 
 // The descriptor layout a translation unit was compiled with.  The host
 // code that writes the descriptors and every unit whose kernels read them

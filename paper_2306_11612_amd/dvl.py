@@ -132,6 +132,7 @@ def lib():
         "dvl_update": (i32, [vp, C.POINTER(dvl_params), C.POINTER(dvl_bins), vp]),
         "dvl_update_noalloc": (i32, [vp, C.POINTER(dvl_params), C.POINTER(dvl_bins), vp]),
         "dvl_update_noalloc_max_bytes": (C.c_size_t, []),
+        "dvl_set_carry_wait": (i32, [i32]),
         "dvl_read_bins": (i32, [vp, C.POINTER(dvl_bins), i32, vp] + [vp] * 9),
         "dvl_export_order": (i32, [vp, vp, vp, vp]),
         "dvl_export_sorted": (i32, [vp, vp, vp, vp]),
@@ -279,6 +280,16 @@ def update_noalloc(vol: "Volume", p: dvl_params, bins: Bins, stream=None):
     b = bins.struct()
     _check(lib().dvl_update_noalloc(vol.handle, C.byref(p), C.byref(b), _stream_ptr(stream)),
            "dvl_update_noalloc")
+
+
+def set_carry_wait(polls: int):
+    """dvl_set_carry_wait: polls of a request's carry flag before a
+    classifying workgroup computes the carry itself (test hook; 0 forces that
+    path)."""
+    _check(lib().dvl_set_carry_wait(int(polls)), "dvl_set_carry_wait")
+
+
+CARRY_WAIT_DEFAULT = 1 << 15
 
 
 def read_bins(vol: "Volume", bins: Bins, stream=None) -> dict:
