@@ -1232,26 +1232,36 @@ __global__ __launch_bounds__(256) void k_bin_stats(BatchDev bd) {
     const int32_t* hb = q.ws.head_bin;
     const int32_t* tb = q.ws.tail_bin;
     // tiles touching bin b: t0 = first with tail >= b, t1 = last with head <= b
-    // (K3a wrote both per bin; t0 is its candidate or the next tile)
+    // (K3a wrote both per bin; t0 is its candidate ta or the next tile)
     const int64_t t1 = uni(gload<int32_t>(q.ws.bin_t1, b));
     const int64_t ta = uni(gload<int32_t>(q.ws.bin_ta, b));
-    const int64_t t0 = (gload<int32_t>(tb, ta) >= b || ta + 1 >= T) ? ta : ta + 1;
+    // then one round of loads: the candidate's tail bin, the last tile's head
+    // and tail bins, the bin's own outputs (written by the rescan when the
+    // bin starts and ends inside one tile) and, per lane, the head and tail
+    // bins and both records of the tiles [ta, t1].  When t0 = ta + 1, tile
+    // ta's bins are all below b and it adds nothing.
+    const int ea = gload<int32_t>(tb, ta);
+    const int h1 = gload<int32_t>(hb, t1), e1 = gload<int32_t>(tb, t1);
+    const uint32_t in_first = gload<uint32_t>(q.first_cell, b), in_last = gload<uint32_t>(q.last_cell, b);
     uint32_t first = 0xFFFFFFFFu, last = 0u;
-    bool inside = false;
-    if (t0 == t1) {
-        const int h0 = gload<int32_t>(hb, t0), e0 = gload<int32_t>(tb, t0);
-        inside = h0 < b && b < e0;
-    }
-    if (inside) {
-        first = gload<uint32_t>(q.first_cell, b);
-        last = gload<uint32_t>(q.last_cell, b);
-    } else {
-        for (int64_t t = t0 + lane; t <= t1; t += kWave) {
-            const int r = gload<int32_t>(hb, t) == b ? 0 : (gload<int32_t>(tb, t) == b ? 1 : -1);
-            if (r < 0) continue;
-            first = min(first, gload<uint32_t>(q.ws.rec_first, r * T + t));
-            last = max(last, gload<uint32_t>(q.ws.rec_last, r * T + t));
+    for (int64_t t = ta + lane; t <= t1; t += kWave) {
+        const int h = gload<int32_t>(hb, t), e = gload<int32_t>(tb, t);
+        const uint32_t f0 = gload<uint32_t>(q.ws.rec_first, t), l0 = gload<uint32_t>(q.ws.rec_last, t);
+        const uint32_t f1 = gload<uint32_t>(q.ws.rec_first, T + t), l1 = gload<uint32_t>(q.ws.rec_last, T + t);
+        if (h == b) {
+            first = min(first, f0);
+            last = max(last, l0);
+        } else if (e == b) {
+            first = min(first, f1);
+            last = max(last, l1);
         }
+    }
+    const int64_t t0 = (ea >= b || ta + 1 >= T) ? ta : ta + 1;
+    const bool inside = t0 == t1 && h1 < b && b < e1;
+    if (inside) {
+        first = in_first;
+        last = in_last;
+    } else {
         first = wave_min_u32(first);
         last = wave_max_u32(last);
     }
