@@ -1327,9 +1327,11 @@ static dvl_status check_no_static_lds(const char* name) {
 
 // Grid of the importance pass.  When the units split evenly over the
 // workgroups that fit the chip at once with `lds` bytes of LDS each (or
-// number no more than them), one round of that many: a workgroup that
-// finishes its unit takes the next one with its tables already in LDS,
-// instead of a second round of workgroups starting cold (descriptors,
+// number no more than them), or belong to several volumes (units of unequal
+// length: the 32-volume batch's pass took 612 instead of 735 us), one round
+// of that many: a workgroup that finishes its unit takes the next one with
+// its tables already in LDS, instead of a second round of workgroups
+// starting cold (descriptors,
 // tables, the first loads: a few dependent memory round trips each), 5 %
 // faster for the 501 M-cell cached-entry pass.  Otherwise 8 workgroups per
 // compute unit, whose later rounds the hardware hands to whichever compute
@@ -1337,7 +1339,7 @@ static dvl_status check_no_static_lds(const char* name) {
 // workgroups of the value path, was 3 % slower).  The occupancy is queried
 // once per kernel and LDS size; any grid gives the same results.
 template <void (*Kernel)(BatchDev)>
-static int64_t resident_grid(size_t lds, int n_cu, int64_t units) {
+static int64_t resident_grid(size_t lds, int n_cu, int64_t units, int n_jobs) {
     static std::atomic<uint64_t> cache{0};   // (lds << 8) | blocks per compute unit, 0: none
     uint64_t c = cache.load(std::memory_order_relaxed);
     int nb = (c >> 8) == (uint64_t)lds && c != 0 ? (int)(c & 0xFF) : 0;
@@ -1352,7 +1354,7 @@ static int64_t resident_grid(size_t lds, int n_cu, int64_t units) {
     }
     const int64_t resident = (int64_t)n_cu * nb;
     if (units <= resident) return std::max<int64_t>(1, units);
-    return units % resident == 0 ? resident : std::min<int64_t>(units, (int64_t)n_cu * 8);
+    return units % resident == 0 || n_jobs > 1 ? resident : std::min<int64_t>(units, (int64_t)n_cu * 8);
 }
 
 template <int MT, typename S, int KR>
@@ -1381,12 +1383,12 @@ static dvl_status launch_typed(const BatchDev& b, int n_cu, hipStream_t s, hipEv
     }
     if (dvl_status st = mark(1)) return st;
     if (b.paths & kPathValues) {
-        const unsigned g = (unsigned)resident_grid<k_tile_sums<MT, S, KR, 0>>(lds1, n_cu, b.k1_units);
+        const unsigned g = (unsigned)resident_grid<k_tile_sums<MT, S, KR, 0>>(lds1, n_cu, b.k1_units, b.n_jobs);
         hipLaunchKernelGGL((k_tile_sums<MT, S, KR, 0>), dim3(g), dim3(kUpdThreads), lds1, s, b);
         DVL_HIP(hipGetLastError());
     }
     if (b.paths & kPathEntries) {
-        const unsigned g = (unsigned)resident_grid<k_tile_sums<MT, S, KR, 1>>(lds1i, n_cu, b.k1_units);
+        const unsigned g = (unsigned)resident_grid<k_tile_sums<MT, S, KR, 1>>(lds1i, n_cu, b.k1_units, b.n_jobs);
         hipLaunchKernelGGL((k_tile_sums<MT, S, KR, 1>), dim3(g), dim3(kUpdThreads), lds1i, s, b);
         DVL_HIP(hipGetLastError());
     }
